@@ -1,0 +1,159 @@
+/*
+ * libctcalign -- CTC forced alignment on AMD Instinct MI355X (gfx950).
+ *
+ * Operation (paper Sec. 4, paragraph "CTC-based forced alignment"): given
+ * per-frame log-probabilities emission[T][C] of a CTC-trained model and a
+ * transcript labels[L] (class ids, none equal to the blank), find the
+ * frame-level alignment of highest total log-probability among all CTC
+ * alignments of the transcript (all frame labellings that collapse to it when
+ * runs are merged and blanks dropped).  This is the Viterbi maximum over the
+ * blank-interleaved trellis of S = 2L+1 states:
+ *
+ *   y'_s = blank (s even), labels[(s-1)/2] (s odd)
+ *   a_0(s) = emission[0][y'_s] for s in {0,1}, -inf otherwise
+ *   a_t(s) = emission[t][y'_s] + max(a_{t-1}(s), a_{t-1}(s-1),
+ *                                     a_{t-1}(s-2) if s odd, s>=3, y'_s != y'_{s-2})
+ *   end state S-1 or S-2 (0 when L = 0), then backtrack.
+ *
+ * Exactness contract: every result is bitwise identical to a plain
+ * sequential float32 evaluation of the recurrence above with one IEEE add
+ * (round to nearest even, denormals kept) per state and frame, the tie rule
+ * "prefer s, then s-1, then s-2" (first maximum under strict '>'), and the
+ * end-state tie resolved to S-1.
+ *
+ * Outputs per utterance:
+ *   out_path[t]   int32  the class id y'_{s_t} aligned to frame t (blanks included)
+ *   out_scores[t] float  emission[t][out_path[t]]
+ *   total         float  a_{T-1}(end state): the alignment's log-probability,
+ *                        equal bitwise to the float32 left fold of out_scores
+ *
+ * Memory: unless stated otherwise every data pointer is a DEVICE pointer
+ * (hipMalloc'd or a torch tensor's data_ptr()) on the context's device; the
+ * caller owns all inputs, outputs and workspaces; the library never frees
+ * or keeps them after the call returns (asynchronous calls: until the
+ * stream reaches the work).  Outputs must not overlap inputs.
+ * Layouts: emission row-major [T][C] float32, row stride C; labels int32.
+ * Limits: 1 <= T <= 2^30, 1 <= C <= 256, 0 <= L, T*(2L+1) < 2^62.
+ *
+ * Errors: every function returns a status (CTCALIGN_OK = 0 on success) and
+ * never aborts.  Argument errors found on the host return CTCALIGN_EINVAL
+ * before any device work and leave outputs untouched.  Per-utterance
+ * conditions found on the device are reported through the status outputs:
+ *   EINVAL      a label outside [0, C) or equal to the blank: path = -1,
+ *               scores = NaN, total = NaN
+ *   EINFEASIBLE no alignment with finite score (e.g. T < L + repeats):
+ *               path = -1, scores = -inf, total = -inf
+ * HIP runtime failures map to CTCALIGN_EDEVICE.
+ *
+ * Threads: a context may be used by one host thread at a time.
+ */
+#ifndef CTCALIGN_H_
+#define CTCALIGN_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CTCALIGN_OK = 0,
+  CTCALIGN_EINVAL = 1,      /* invalid argument or label */
+  CTCALIGN_EINFEASIBLE = 2, /* no alignment with finite score */
+  CTCALIGN_ENOMEM = 3,      /* allocation failed or over the memory budget */
+  CTCALIGN_EDEVICE = 4,     /* HIP runtime error or device-side watchdog */
+  CTCALIGN_EAGAIN = 5,      /* server queue full (non-blocking submit) */
+  CTCALIGN_EBUSY = 6        /* request not finished yet (poll) */
+};
+
+typedef struct ctcalign_ctx ctcalign_ctx;
+typedef struct ctcalign_plan ctcalign_plan;
+typedef struct ctcalign_server ctcalign_server;
+typedef void *ctcalign_stream; /* a hipStream_t; NULL = the context's stream */
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *ctcalign_strerror(int status);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int ctcalign_version(void);
+
+/* ---- contexts ----------------------------------------------------------- */
+
+/* Creates a context on HIP device `device` (or the current device if < 0):
+ * a stream, a cached workspace arena and the tuning table.  *ctx receives
+ * the handle.  Errors: EINVAL (ctx NULL), EDEVICE. */
+int ctcalign_ctx_create(int device, ctcalign_ctx **ctx);
+
+/* Waits for the context's stream, frees everything it owns.  NULL is a no-op. */
+int ctcalign_ctx_destroy(ctcalign_ctx *ctx);
+
+/* Bytes of backpointer workspace one alignment of shape (T, L, C) needs under
+ * the geometry this context would pick; 0 on invalid shape.  Depends on the
+ * tuning table: query again after ctcalign_tune. */
+size_t ctcalign_workspace_bytes(ctcalign_ctx *ctx, int32_t T, int32_t L, int32_t C);
+
+/* ---- one utterance ------------------------------------------------------ */
+
+/* Aligns one utterance on the default context (created on first use on the
+ * current device) and its stream, and waits for the result.
+ * Returns OK, EINVAL, EINFEASIBLE (device-side outcome), ENOMEM or EDEVICE. */
+int ctcalign_align(const float *emission, int32_t T, int32_t C,
+                   const int32_t *labels, int32_t L, int32_t blank,
+                   int32_t *out_path, float *out_scores);
+
+/* Asynchronous single alignment on `stream` (NULL: the context's stream).
+ * out_total (device, 1 float) and out_status (device, 1 int32) may be NULL.
+ * workspace (device, >= ctcalign_workspace_bytes, 256-byte aligned) may be
+ * NULL: the context's arena is used (then calls on one context serialise on
+ * its arena).  Returns OK when the launch was queued; the alignment's own
+ * status is written to *out_status. */
+int ctcalign_align_ex(ctcalign_ctx *ctx, const float *emission, int32_t T, int32_t C,
+                      const int32_t *labels, int32_t L, int32_t blank,
+                      int32_t *out_path, float *out_scores, float *out_total,
+                      int32_t *out_status, void *workspace, size_t ws_bytes,
+                      ctcalign_stream stream);
+
+/* ---- many utterances: one persistent kernel over a device work queue ---- */
+
+/* Builds a plan for N utterances packed in flat device arrays.  Host arrays
+ * (length N): em_off (element offset of each [T_i][C_i] emission in
+ * `emissions`), T, C, lab_off (element offset in `labels`), L, frame_off
+ * (element offset of each utterance's T_i outputs in out_paths/out_scores).
+ * out_totals and out_status are device arrays of N entries.  The plan sorts
+ * utterances longest first, picks each one's geometry from the tuning table,
+ * uploads the descriptors, allocates the backpointer workspace and captures
+ * the whole launch (queue reset + persistent kernel) in a HIP graph.
+ * Emission rows must not straddle other utterances' outputs.
+ * Errors: EINVAL (bad shape or pointer), ENOMEM, EDEVICE. */
+int ctcalign_plan_create(ctcalign_ctx *ctx, int32_t N,
+                         const float *emissions, const int64_t *em_off,
+                         const int32_t *T, const int32_t *C,
+                         const int32_t *labels, const int64_t *lab_off,
+                         const int32_t *L, int32_t blank,
+                         int32_t *out_paths, float *out_scores, const int64_t *frame_off,
+                         float *out_totals, int32_t *out_status,
+                         ctcalign_plan **plan);
+
+/* Replays the plan's graph on `stream` (NULL: the context's stream).
+ * Asynchronous; per-utterance statuses land in out_status. */
+int ctcalign_plan_run(ctcalign_plan *plan, ctcalign_stream stream);
+
+/* Frees the plan (waits for its last run).  NULL is a no-op. */
+int ctcalign_plan_destroy(ctcalign_plan *plan);
+
+/* One-shot batched alignment: plan_create + plan_run + plan_destroy, with the
+ * plan cached on the context while the same arguments come back. */
+int ctcalign_align_batched(ctcalign_ctx *ctx, int32_t N,
+                           const float *emissions, const int64_t *em_off,
+                           const int32_t *T, const int32_t *C,
+                           const int32_t *labels, const int64_t *lab_off,
+                           const int32_t *L, int32_t blank,
+                           int32_t *out_paths, float *out_scores, const int64_t *frame_off,
+                           float *out_totals, int32_t *out_status,
+                           ctcalign_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CTCALIGN_H_ */

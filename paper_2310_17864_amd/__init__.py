@@ -1,0 +1,189 @@
+"""libctcalign: CTC forced alignment on AMD MI355X (gfx950).
+
+Python face of the C library (include/ctcalign.h).  PyTorch provides device
+memory and streams; every step of the alignment runs in hand-written HIP
+kernels, and there is no CPU fallback: without the built library or a GPU
+these functions raise.
+
+    path, scores, total, status = align(emission_cuda_f32[T, C], labels_cuda_i32[L])
+
+The method is the paper's forced alignment (Sec. 4, paragraph "CTC-based
+forced alignment"): the highest-scoring CTC alignment of a transcript to
+per-frame log-probabilities, with per-frame label ids and scores.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import (CtcAlignError, EAGAIN, EBUSY, EDEVICE, EINFEASIBLE, EINVAL, ENOMEM, OK,
+                   LibraryMissing, strerror)
+
+__all__ = ["align", "align_many_launches", "Context", "Plan", "workspace_bytes", "strerror",
+           "CtcAlignError", "LibraryMissing", "OK", "EINVAL", "EINFEASIBLE", "ENOMEM",
+           "EDEVICE", "EAGAIN", "EBUSY"]
+
+_contexts: Dict[int, "Context"] = {}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(device) -> int:
+    torch = _torch()
+    return int(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """A library context on one device (stream, workspace arena, tuning table)."""
+
+    def __init__(self, device: int = 0):
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        _lib.check(lib.ctcalign_ctx_create(int(device), ctypes.byref(h)), "ctx_create")
+        self.handle = h
+        self.device = int(device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.load().ctcalign_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, T: int, L: int, C: int) -> int:
+        return int(_lib.load().ctcalign_workspace_bytes(self.handle, T, L, C))
+
+
+def context(device: Optional[int] = None) -> Context:
+    torch = _torch()
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _contexts:
+        _contexts[dev] = Context(dev)
+    return _contexts[dev]
+
+
+def workspace_bytes(T: int, L: int, C: int, device: Optional[int] = None) -> int:
+    return context(device).workspace_bytes(T, L, C)
+
+
+def _check_dev_tensor(x, dtype, name):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def align(emission, labels, blank: int = 0, out=None, workspace=None, sync: bool = True):
+    """Forced alignment of one utterance on the current stream.
+
+    emission: float32 [T, C] device tensor (log-probabilities); labels: int32
+    [L] device tensor.  Returns (path int32[T], scores float32[T],
+    total float32[1], status int32[1]) device tensors; with sync=True the
+    call waits and raises CtcAlignError on EINVAL / EINFEASIBLE.
+    """
+    torch = _torch()
+    _check_dev_tensor(emission, torch.float32, "emission")
+    _check_dev_tensor(labels, torch.int32, "labels")
+    if emission.dim() != 2:
+        raise ValueError("emission must be [T, C]")
+    T, C = emission.shape
+    L = labels.numel()
+    dev = emission.device
+    ctx = context(dev.index)
+    if out is None:
+        path = torch.empty(T, dtype=torch.int32, device=dev)
+        scores = torch.empty(T, dtype=torch.float32, device=dev)
+        total = torch.empty(1, dtype=torch.float32, device=dev)
+        status = torch.empty(1, dtype=torch.int32, device=dev)
+    else:
+        path, scores, total, status = out
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    rc = _lib.load().ctcalign_align_ex(
+        ctx.handle, emission.data_ptr(), T, C, labels.data_ptr() if L else None, L, blank,
+        path.data_ptr(), scores.data_ptr(), total.data_ptr(), status.data_ptr(),
+        ws_ptr, ws_bytes, _stream_handle(dev))
+    _lib.check(rc, "align")
+    if sync:
+        st = int(status.item())
+        if st != OK:
+            raise CtcAlignError(st, "align")
+    return path, scores, total, status
+
+
+def align_many_launches(emissions: Sequence, labels: Sequence, blank: int = 0):
+    """One kernel launch per utterance, all on the current stream (the plain
+    per-utterance method).  Returns a list of (path, scores, total, status)."""
+    return [align(e, l, blank, sync=False) for e, l in zip(emissions, labels)]
+
+
+class Plan:
+    """Batched alignment of many utterances packed in flat device buffers:
+    sorted longest first into a device work queue drained by one persistent
+    kernel, the whole launch captured in a HIP graph and replayed by run()."""
+
+    def __init__(self, emissions, em_off, T, C, labels, lab_off, L, frame_off, blank: int = 0,
+                 outputs=None, ctx: Optional[Context] = None):
+        torch = _torch()
+        _check_dev_tensor(emissions, torch.float32, "emissions")
+        _check_dev_tensor(labels, torch.int32, "labels")
+        dev = emissions.device
+        self.ctx = ctx or context(dev.index)
+        self.n = n = int(len(T))
+        frames = int(np.sum(np.asarray(T, dtype=np.int64)))
+        self.host = {
+            "em_off": np.ascontiguousarray(em_off, dtype=np.int64),
+            "T": np.ascontiguousarray(T, dtype=np.int32),
+            "C": np.ascontiguousarray(C, dtype=np.int32),
+            "lab_off": np.ascontiguousarray(lab_off, dtype=np.int64),
+            "L": np.ascontiguousarray(L, dtype=np.int32),
+            "frame_off": np.ascontiguousarray(frame_off, dtype=np.int64),
+        }
+        if outputs is None:
+            self.paths = torch.empty(max(frames, 1), dtype=torch.int32, device=dev)
+            self.scores = torch.empty(max(frames, 1), dtype=torch.float32, device=dev)
+            self.totals = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+            self.status = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        else:
+            self.paths, self.scores, self.totals, self.status = outputs
+        self._keep = (emissions, labels)
+        h = self.host
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        handle = ctypes.c_void_p()
+        rc = _lib.load().ctcalign_plan_create(
+            self.ctx.handle, n, emissions.data_ptr(), ptr(h["em_off"]), ptr(h["T"]), ptr(h["C"]),
+            labels.data_ptr(), ptr(h["lab_off"]), ptr(h["L"]), blank,
+            self.paths.data_ptr(), self.scores.data_ptr(), ptr(h["frame_off"]),
+            self.totals.data_ptr(), self.status.data_ptr(), ctypes.byref(handle))
+        _lib.check(rc, "plan_create")
+        self.handle = handle
+
+    def run(self, stream=None):
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream(self.paths.device)
+        _lib.check(_lib.load().ctcalign_plan_run(self.handle, int(s.cuda_stream)), "plan_run")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.load().ctcalign_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,565 @@
+// Host side of libctcalign: argument checks, contexts, geometry choice,
+// workspace arenas, launches and the batched plan (sorted work queue +
+// captured HIP graph).  Every computation runs in the gfx950 kernels; this
+// file only prepares descriptors and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/ctcalign.h"
+#include "internal.hpp"
+#include "kernels.hpp"
+#include "tune.hpp"
+
+using namespace ctca;
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr int64_t kMaxS = 16 * kWave * 32;     // largest trellis one workgroup holds
+
+int log_level() {
+  static int lv = [] {
+    const char* e = std::getenv("CTCALIGN_LOG");
+    return e ? std::atoi(e) : 0;
+  }();
+  return lv;
+}
+
+#define CTCA_LOG(lvl, ...)                       \
+  do {                                           \
+    if (log_level() >= (lvl)) {                  \
+      std::fprintf(stderr, "[ctcalign] " __VA_ARGS__); \
+      std::fputc('\n', stderr);                  \
+    }                                            \
+  } while (0)
+
+int map_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return CTCALIGN_OK;
+  CTCA_LOG(1, "%s: %s", what, hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? CTCALIGN_ENOMEM : CTCALIGN_EDEVICE;
+}
+
+#define HIP_TRY(expr)                                 \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) return map_hip(_e, #expr);  \
+  } while (0)
+
+// Device buffer that only grows.
+struct Arena {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  int reserve(size_t need) {
+    if (need <= bytes) return CTCALIGN_OK;
+    if (ptr) {
+      (void)hipFree(ptr);
+      ptr = nullptr;
+      bytes = 0;
+    }
+    size_t sz = std::max(need, (size_t)1 << 20);
+    if (hipMalloc(&ptr, sz) != hipSuccess) {
+      ptr = nullptr;
+      return CTCALIGN_ENOMEM;
+    }
+    bytes = sz;
+    return CTCALIGN_OK;
+  }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+};
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int row_stride_for(int C) { return C <= 32 ? 32 : 256; }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace
+
+struct ctcalign_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 0;
+  Arena ws;        // backpointer workspace for single alignments
+  Arena pad;       // padded emission copies for single alignments
+  int32_t* h_status = nullptr;   // pinned
+  int32_t* d_status = nullptr;
+  float* d_total = nullptr;
+  ctca::TuneTable tune;
+  ctcalign_plan* cached = nullptr;
+  uint64_t cached_key = 0;
+};
+
+struct ctcalign_plan {
+  ctcalign_ctx* ctx = nullptr;
+  int32_t n = 0;
+  int npacks = 0;
+  int grid = 0;
+  Inst* d_insts = nullptr;
+  Pack* d_packs = nullptr;
+  PadDesc* d_pad = nullptr;
+  int npad = 0;
+  int64_t pad_max = 0;
+  int* d_head = nullptr;
+  void* d_bp = nullptr;
+  size_t bp_bytes = 0;
+  void* d_padbuf = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+};
+
+namespace {
+
+std::mutex g_default_mu;
+ctcalign_ctx* g_default[kMaxDevices] = {};
+
+int validate_one(const float* em, int32_t T, int32_t C, const int32_t* labels, int32_t L,
+                 int32_t blank, const void* path, const void* scores) {
+  if (!em || !path || !scores) return CTCALIGN_EINVAL;
+  if (T < 1 || T > (1 << 30) || C < 1 || C > kMaxC || L < 0) return CTCALIGN_EINVAL;
+  if (L > 0 && !labels) return CTCALIGN_EINVAL;
+  if (blank < 0 || blank >= C) return CTCALIGN_EINVAL;
+  if (2 * (int64_t)L + 1 > kMaxS) return CTCALIGN_EINVAL;
+  return CTCALIGN_OK;
+}
+
+// Fills geometry and LDS stride fields of an Inst for a single launch.
+void geometry_one(const ctcalign_ctx* ctx, Inst& in) {
+  const int S = 2 * in.L + 1;
+  const Geo g = ctx->tune.pick_one(S, in.C);
+  in.W = g.W;
+  in.M = g.M;
+}
+
+int launch_single(ctcalign_ctx* ctx, const float* emission, int32_t T, int32_t C,
+                  const int32_t* labels, int32_t L, int32_t blank, int32_t* out_path,
+                  float* out_scores, float* out_total, int32_t* out_status, void* workspace,
+                  size_t ws_bytes, hipStream_t st) {
+  int rc = validate_one(emission, T, C, labels, L, blank, out_path, out_scores);
+  if (rc) return rc;
+  Inst in{};
+  in.T = T;
+  in.C = C;
+  in.L = L;
+  in.blank = blank;
+  in.lab = labels;
+  in.path = out_path;
+  in.scores = out_scores;
+  in.total = out_total;
+  in.status = out_status;
+  in.stride = row_stride_for(C);
+  in.prio = 0;
+  geometry_one(ctx, in);
+  if (!geometry_supported_one(in.W, in.M)) return CTCALIGN_EINVAL;
+
+  const size_t need = round_up((size_t)bp_words(T, in.W, in.M) * 4, 256);
+  if (workspace) {
+    if (ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255u)) return CTCALIGN_EINVAL;
+    in.bp = static_cast<uint32_t*>(workspace);
+  } else {
+    rc = ctx->ws.reserve(need);
+    if (rc) return rc;
+    in.bp = static_cast<uint32_t*>(ctx->ws.ptr);
+  }
+
+  if (C == in.stride && aligned16(emission)) {
+    in.em = emission;
+  } else {
+    // re-layout rows to the compiled stride in the context's pad buffer
+    rc = ctx->pad.reserve((size_t)T * in.stride * sizeof(float));
+    if (rc) return rc;
+    const PadDesc pd{emission, static_cast<float*>(ctx->pad.ptr), T, C, in.stride, 0};
+    HIP_TRY(launch_pad_one(pd, st));
+    in.em = static_cast<float*>(ctx->pad.ptr);
+  }
+  CTCA_LOG(2, "align T=%d C=%d L=%d -> W=%d M=%d stride=%d", T, C, L, in.W, in.M, in.stride);
+  HIP_TRY(launch_one(in, st));
+  return CTCALIGN_OK;
+}
+
+uint64_t fnv(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ctcalign_strerror(int status) {
+  switch (status) {
+    case CTCALIGN_OK: return "ok";
+    case CTCALIGN_EINVAL: return "invalid argument or label";
+    case CTCALIGN_EINFEASIBLE: return "no alignment with finite score";
+    case CTCALIGN_ENOMEM: return "out of memory or over budget";
+    case CTCALIGN_EDEVICE: return "HIP runtime error or device watchdog";
+    case CTCALIGN_EAGAIN: return "queue full, try again";
+    case CTCALIGN_EBUSY: return "not finished yet";
+    default: return "unknown status";
+  }
+}
+
+int ctcalign_version(void) { return 100; }
+
+int ctcalign_ctx_create(int device, ctcalign_ctx** out) {
+  if (!out) return CTCALIGN_EINVAL;
+  *out = nullptr;
+  if (device < 0) HIP_TRY(hipGetDevice(&device));
+  HIP_TRY(hipSetDevice(device));
+  ctcalign_ctx* c = new (std::nothrow) ctcalign_ctx();
+  if (!c) return CTCALIGN_ENOMEM;
+  c->device = device;
+  int rc = CTCALIGN_OK;
+  hipDeviceProp_t prop;
+  if ((rc = map_hip(hipGetDeviceProperties(&prop, device), "props")) ||
+      (rc = map_hip(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "stream")) ||
+      (rc = map_hip(hipHostMalloc((void**)&c->h_status, 16 * sizeof(int32_t)), "pinned")) ||
+      (rc = map_hip(hipMalloc((void**)&c->d_status, 16 * sizeof(int32_t)), "status")) ||
+      (rc = map_hip(hipMalloc((void**)&c->d_total, 16 * sizeof(float)), "total"))) {
+    ctcalign_ctx_destroy(c);
+    return rc;
+  }
+  c->num_cu = prop.multiProcessorCount;
+  c->tune.load_default(c->num_cu);
+  *out = c;
+  return CTCALIGN_OK;
+}
+
+int ctcalign_ctx_destroy(ctcalign_ctx* c) {
+  if (!c) return CTCALIGN_OK;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->cached) ctcalign_plan_destroy(c->cached);
+  c->ws.release();
+  c->pad.release();
+  if (c->h_status) (void)hipHostFree(c->h_status);
+  if (c->d_status) (void)hipFree(c->d_status);
+  if (c->d_total) (void)hipFree(c->d_total);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  {
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    for (auto& d : g_default)
+      if (d == c) d = nullptr;
+  }
+  delete c;
+  return CTCALIGN_OK;
+}
+
+size_t ctcalign_workspace_bytes(ctcalign_ctx* ctx, int32_t T, int32_t L, int32_t C) {
+  if (!ctx || T < 1 || L < 0 || C < 1 || C > kMaxC || 2 * (int64_t)L + 1 > kMaxS) return 0;
+  const Geo g = ctx->tune.pick_one(2 * L + 1, C);
+  return round_up((size_t)bp_words(T, g.W, g.M) * 4, 256);
+}
+
+int ctcalign_align_ex(ctcalign_ctx* ctx, const float* emission, int32_t T, int32_t C,
+                      const int32_t* labels, int32_t L, int32_t blank, int32_t* out_path,
+                      float* out_scores, float* out_total, int32_t* out_status, void* workspace,
+                      size_t ws_bytes, ctcalign_stream stream) {
+  if (!ctx) return CTCALIGN_EINVAL;
+  int rc = validate_one(emission, T, C, labels, L, blank, out_path, out_scores);
+  if (rc) return rc;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+  return launch_single(ctx, emission, T, C, labels, L, blank, out_path, out_scores, out_total,
+                       out_status, workspace, ws_bytes, st);
+}
+
+int ctcalign_align(const float* emission, int32_t T, int32_t C, const int32_t* labels, int32_t L,
+                   int32_t blank, int32_t* out_path, float* out_scores) {
+  int rc = validate_one(emission, T, C, labels, L, blank, out_path, out_scores);
+  if (rc) return rc;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return CTCALIGN_EDEVICE;
+  ctcalign_ctx* ctx;
+  {
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    if (!g_default[dev]) {
+      rc = ctcalign_ctx_create(dev, &g_default[dev]);
+      if (rc) return rc;
+    }
+    ctx = g_default[dev];
+  }
+  rc = launch_single(ctx, emission, T, C, labels, L, blank, out_path, out_scores, ctx->d_total,
+                     ctx->d_status, nullptr, 0, ctx->stream);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(ctx->h_status, ctx->d_status, sizeof(int32_t), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return ctx->h_status[0];
+}
+
+// ---- batched plans -----------------------------------------------------------
+
+int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
+                         const int64_t* em_off, const int32_t* T, const int32_t* C,
+                         const int32_t* labels, const int64_t* lab_off, const int32_t* L,
+                         int32_t blank, int32_t* out_paths, float* out_scores,
+                         const int64_t* frame_off, float* out_totals, int32_t* out_status,
+                         ctcalign_plan** plan_out) {
+  if (!ctx || !plan_out || N < 0) return CTCALIGN_EINVAL;
+  *plan_out = nullptr;
+  if (N > 0 && (!emissions || !em_off || !T || !C || !lab_off || !L || !out_paths ||
+                !out_scores || !frame_off || !out_totals || !out_status))
+    return CTCALIGN_EINVAL;
+  for (int i = 0; i < N; ++i) {
+    if (T[i] < 1 || T[i] > (1 << 30) || C[i] < 1 || C[i] > kMaxC || L[i] < 0 || blank < 0 ||
+        blank >= C[i] || em_off[i] < 0 || lab_off[i] < 0 || frame_off[i] < 0)
+      return CTCALIGN_EINVAL;
+    if (L[i] > 0 && !labels) return CTCALIGN_EINVAL;
+    if (2 * (int64_t)L[i] + 1 > ctx->tune.max_pack_states()) return CTCALIGN_EINVAL;
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+
+  ctcalign_plan* p = new (std::nothrow) ctcalign_plan();
+  if (!p) return CTCALIGN_ENOMEM;
+  p->ctx = ctx;
+  p->n = N;
+
+  std::vector<Inst> insts(N);
+  std::vector<PadDesc> pads;
+  std::vector<double> cost(N);
+  size_t bp_total = 0, pad_total = 0;
+  std::vector<size_t> bp_off(N), pad_off(N, SIZE_MAX);
+  for (int i = 0; i < N; ++i) {
+    Inst& in = insts[i];
+    in.T = T[i];
+    in.C = C[i];
+    in.L = L[i];
+    in.blank = blank;
+    in.lab = labels ? labels + lab_off[i] : nullptr;
+    in.path = out_paths + frame_off[i];
+    in.scores = out_scores + frame_off[i];
+    in.total = out_totals + i;
+    in.status = out_status + i;
+    in.stride = row_stride_for(C[i]);
+    const Geo g = ctx->tune.pick_pack(2 * L[i] + 1, C[i], T[i]);
+    in.W = g.W;
+    in.M = g.M;
+    in.prio = 0;
+    cost[i] = (double)T[i] * ctx->tune.step_cost(g, in.stride);
+    bp_off[i] = bp_total;
+    bp_total += round_up((size_t)bp_words(T[i], in.W, in.M) * 4, 256);
+    const float* src = emissions + em_off[i];
+    if (C[i] != in.stride || !aligned16(src)) {
+      pad_off[i] = pad_total;
+      pad_total += round_up((size_t)T[i] * in.stride * sizeof(float), 256);
+    }
+  }
+
+  // LPT order: most expensive first
+  std::vector<int> order(N);
+  for (int i = 0; i < N; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+
+  // packs of 4 waves: W=4 alone, W=2 in pairs, W=1 in fours (neighbours in
+  // cost order, so a pack's waves finish at similar times)
+  std::vector<Pack> packs;
+  std::vector<double> pack_cost;
+  Pack open2{}, open1{};
+  int n2 = 0, n1 = 0;
+  double c2 = 0, c1 = 0;
+  auto blank_pack = [] {
+    Pack pk;
+    for (int k = 0; k < kPackWaves; ++k) {
+      pk.inst[k] = -1;
+      pk.seg[k] = 0;
+      pk.first[k] = (int16_t)k;
+    }
+    return pk;
+  };
+  open2 = blank_pack();
+  open1 = blank_pack();
+  for (int idx : order) {
+    const int W = insts[idx].W;
+    if (W == 4) {
+      Pack pk = blank_pack();
+      for (int k = 0; k < 4; ++k) {
+        pk.inst[k] = idx;
+        pk.seg[k] = (int16_t)k;
+        pk.first[k] = 0;
+      }
+      packs.push_back(pk);
+      pack_cost.push_back(cost[idx]);
+    } else if (W == 2) {
+      for (int k = 0; k < 2; ++k) {
+        open2.inst[2 * n2 + k] = idx;
+        open2.seg[2 * n2 + k] = (int16_t)k;
+        open2.first[2 * n2 + k] = (int16_t)(2 * n2);
+      }
+      c2 = std::max(c2, cost[idx]);
+      if (++n2 == 2) {
+        packs.push_back(open2);
+        pack_cost.push_back(c2);
+        open2 = blank_pack();
+        n2 = 0;
+        c2 = 0;
+      }
+    } else {
+      open1.inst[n1] = idx;
+      open1.seg[n1] = 0;
+      open1.first[n1] = (int16_t)n1;
+      c1 = std::max(c1, cost[idx]);
+      if (++n1 == 4) {
+        packs.push_back(open1);
+        pack_cost.push_back(c1);
+        open1 = blank_pack();
+        n1 = 0;
+        c1 = 0;
+      }
+    }
+  }
+  if (n2) {
+    packs.push_back(open2);
+    pack_cost.push_back(c2);
+  }
+  if (n1) {
+    packs.push_back(open1);
+    pack_cost.push_back(c1);
+  }
+  {
+    std::vector<int> po(packs.size());
+    for (size_t i = 0; i < po.size(); ++i) po[i] = (int)i;
+    std::stable_sort(po.begin(), po.end(), [&](int a, int b) { return pack_cost[a] > pack_cost[b]; });
+    std::vector<Pack> sorted(packs.size());
+    for (size_t i = 0; i < po.size(); ++i) sorted[i] = packs[po[i]];
+    packs.swap(sorted);
+  }
+  p->npacks = (int)packs.size();
+  ctx->tune.assign_priorities(insts, packs);
+
+  int rc = CTCALIGN_OK;
+  auto fail = [&](int code) {
+    ctcalign_plan_destroy(p);
+    return code;
+  };
+  p->bp_bytes = std::max(bp_total, (size_t)256);
+  if ((rc = map_hip(hipMalloc(&p->d_bp, p->bp_bytes), "bp"))) return fail(rc);
+  if (pad_total && (rc = map_hip(hipMalloc(&p->d_padbuf, pad_total), "padbuf"))) return fail(rc);
+  for (int i = 0; i < N; ++i) {
+    Inst& in = insts[i];
+    in.bp = reinterpret_cast<uint32_t*>(static_cast<char*>(p->d_bp) + bp_off[i]);
+    const float* src = emissions + em_off[i];
+    if (pad_off[i] != SIZE_MAX) {
+      float* dst = reinterpret_cast<float*>(static_cast<char*>(p->d_padbuf) + pad_off[i]);
+      pads.push_back(PadDesc{src, dst, in.T, in.C, in.stride, 0});
+      p->pad_max = std::max(p->pad_max, (int64_t)in.T * in.stride);
+      in.em = dst;
+    } else {
+      in.em = src;
+    }
+  }
+  p->npad = (int)pads.size();
+  if ((rc = map_hip(hipMalloc((void**)&p->d_insts, sizeof(Inst) * std::max(N, 1)), "insts")) ||
+      (rc = map_hip(hipMalloc((void**)&p->d_packs, sizeof(Pack) * std::max(p->npacks, 1)), "packs")) ||
+      (rc = map_hip(hipMalloc((void**)&p->d_head, sizeof(int)), "head")))
+    return fail(rc);
+  if (p->npad && (rc = map_hip(hipMalloc((void**)&p->d_pad, sizeof(PadDesc) * p->npad), "pad")))
+    return fail(rc);
+  if (N && (rc = map_hip(hipMemcpy(p->d_insts, insts.data(), sizeof(Inst) * N, hipMemcpyHostToDevice), "h2d")))
+    return fail(rc);
+  if (p->npacks && (rc = map_hip(hipMemcpy(p->d_packs, packs.data(), sizeof(Pack) * p->npacks,
+                                           hipMemcpyHostToDevice), "h2d")))
+    return fail(rc);
+  if (p->npad && (rc = map_hip(hipMemcpy(p->d_pad, pads.data(), sizeof(PadDesc) * p->npad,
+                                         hipMemcpyHostToDevice), "h2d")))
+    return fail(rc);
+
+  p->grid = std::min(p->npacks, ctx->num_cu * persistent_blocks_per_cu());
+  if (p->grid < 1) p->grid = 1;
+
+  // capture: [pad] -> queue reset -> persistent kernel
+  if ((rc = map_hip(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "capstream")))
+    return fail(rc);
+  if ((rc = map_hip(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal), "capture")))
+    return fail(rc);
+  hipError_t e = hipSuccess;
+  if (p->npad) e = launch_pad(p->d_pad, p->npad, p->pad_max, p->cap_stream);
+  if (e == hipSuccess) e = launch_fill(p->d_head, 1, 0, p->cap_stream);
+  if (e == hipSuccess && p->npacks)
+    e = launch_persistent(p->d_insts, p->d_packs, p->npacks, p->d_head, p->grid, p->cap_stream);
+  hipError_t e2 = hipStreamEndCapture(p->cap_stream, &p->graph);
+  if (e != hipSuccess) return fail(map_hip(e, "captured launch"));
+  if ((rc = map_hip(e2, "end capture"))) return fail(rc);
+  if ((rc = map_hip(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0), "instantiate")))
+    return fail(rc);
+  CTCA_LOG(2, "plan: N=%d packs=%d grid=%d bp=%zu pad=%zu", N, p->npacks, p->grid, bp_total, pad_total);
+  *plan_out = p;
+  return CTCALIGN_OK;
+}
+
+int ctcalign_plan_run(ctcalign_plan* p, ctcalign_stream stream) {
+  if (!p) return CTCALIGN_EINVAL;
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : p->ctx->stream;
+  HIP_TRY(hipGraphLaunch(p->exec, st));
+  return CTCALIGN_OK;
+}
+
+int ctcalign_plan_destroy(ctcalign_plan* p) {
+  if (!p) return CTCALIGN_OK;
+  (void)hipSetDevice(p->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->d_insts) (void)hipFree(p->d_insts);
+  if (p->d_packs) (void)hipFree(p->d_packs);
+  if (p->d_pad) (void)hipFree(p->d_pad);
+  if (p->d_head) (void)hipFree(p->d_head);
+  if (p->d_bp) (void)hipFree(p->d_bp);
+  if (p->d_padbuf) (void)hipFree(p->d_padbuf);
+  if (p->ctx && p->ctx->cached == p) p->ctx->cached = nullptr;
+  delete p;
+  return CTCALIGN_OK;
+}
+
+int ctcalign_align_batched(ctcalign_ctx* ctx, int32_t N, const float* emissions,
+                           const int64_t* em_off, const int32_t* T, const int32_t* C,
+                           const int32_t* labels, const int64_t* lab_off, const int32_t* L,
+                           int32_t blank, int32_t* out_paths, float* out_scores,
+                           const int64_t* frame_off, float* out_totals, int32_t* out_status,
+                           ctcalign_stream stream) {
+  if (!ctx || N < 0) return CTCALIGN_EINVAL;
+  if (N > 0 && (!em_off || !T || !C || !lab_off || !L || !frame_off)) return CTCALIGN_EINVAL;
+  uint64_t h = 1469598103934665603ull;
+  const void* ptrs[] = {emissions, labels, out_paths, out_scores, out_totals, out_status};
+  h = fnv(h, ptrs, sizeof(ptrs));
+  h = fnv(h, &N, sizeof(N));
+  h = fnv(h, &blank, sizeof(blank));
+  if (N > 0) {
+    h = fnv(h, em_off, sizeof(int64_t) * N);
+    h = fnv(h, T, sizeof(int32_t) * N);
+    h = fnv(h, C, sizeof(int32_t) * N);
+    h = fnv(h, lab_off, sizeof(int64_t) * N);
+    h = fnv(h, L, sizeof(int32_t) * N);
+    h = fnv(h, frame_off, sizeof(int64_t) * N);
+  }
+  if (!ctx->cached || ctx->cached_key != h) {
+    if (ctx->cached) ctcalign_plan_destroy(ctx->cached);
+    ctcalign_plan* p = nullptr;
+    int rc = ctcalign_plan_create(ctx, N, emissions, em_off, T, C, labels, lab_off, L, blank,
+                                  out_paths, out_scores, frame_off, out_totals, out_status, &p);
+    if (rc) return rc;
+    ctx->cached = p;
+    ctx->cached_key = h;
+  }
+  return ctcalign_plan_run(ctx->cached, stream);
+}
+
+}  // extern "C"

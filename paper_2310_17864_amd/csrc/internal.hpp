@@ -1,0 +1,64 @@
+// Types shared by the host library and the gfx950 kernels.
+#pragma once
+#include <stdint.h>
+
+namespace ctca {
+
+constexpr int kWave = 64;       // lanes per wavefront (CDNA)
+constexpr int kBlk = 32;        // frames per backpointer word
+constexpr int kUnroll = 8;      // frames per unrolled group in the forward loop
+constexpr int kChunk = 4;       // emission rows per staged chunk
+constexpr int kRing = 8;        // emission rows held in a wave's LDS ring
+constexpr int kBnd = 128;       // boundary values held between two segments
+constexpr int kMaxC = 256;      // largest class count served by the LDS ring
+constexpr int kPackWaves = 4;   // waves per workgroup in the persistent kernels
+
+// Device status codes (same values as the public header).
+enum : int32_t { kOk = 0, kEinval = 1, kEinfeasible = 2, kEnomem = 3, kEdevice = 4 };
+
+// One alignment as the kernels see it.  The trellis of S = 2L+1 states is cut
+// into W segments of 64*M states; segment w runs on one wavefront and lane l
+// of it owns states [w*64*M + l*M, w*64*M + (l+1)*M).
+struct Inst {
+  const float* em;     // [T][stride]: row t at em + t*stride (stride >= C)
+  const int32_t* lab;  // [L]
+  int32_t* path;       // [T]
+  float* scores;       // [T]
+  uint32_t* bp;        // backpointer planes, bp_words(T, W, M) words
+  float* total;        // nullable
+  int32_t* status;     // nullable
+  int32_t T, C, L, blank;
+  int32_t W, M;        // geometry
+  int32_t stride;      // emission row stride in HBM and LDS: 32 or 256
+  int32_t prio;        // wave issue priority 0..3
+};
+
+// A workgroup-sized work item of the persistent kernel: wave k runs segment
+// seg[k] of instance inst[k] (inst < 0: idle); the W segments of an instance
+// sit on consecutive waves starting at first[k].
+struct Pack {
+  int32_t inst[kPackWaves];
+  int16_t seg[kPackWaves];
+  int16_t first[kPackWaves];
+};
+
+// Row re-layout of one emission into the compiled LDS stride.
+struct PadDesc {
+  const float* src;   // [T][C]
+  float* dst;         // [T][stride]
+  int32_t T, C, stride, pad_;
+};
+
+// Number of 32-frame backpointer blocks (frames 1..T-1 carry backpointers).
+__host__ __device__ inline int64_t bp_blocks(int64_t T) { return (T - 1 + kBlk - 1) / kBlk; }
+
+// Planes per segment and block: one "moved" plane per state slot, plus one
+// "skipped" plane per odd (label) slot -> 3M/2 words per lane.
+__host__ __device__ inline int bp_planes(int M) { return 3 * M / 2; }
+
+// Words of backpointers for an instance: [W][blocks][planes][64 lanes].
+__host__ __device__ inline int64_t bp_words(int64_t T, int W, int M) {
+  return (int64_t)W * bp_blocks(T) * bp_planes(M) * kWave;
+}
+
+}  // namespace ctca

@@ -1,0 +1,97 @@
+// Geometry choice: how many wavefronts (W) and states per lane (M) an
+// alignment of S states gets, for a single launch and inside the batched
+// persistent kernel.  Defaults come from a cost model; ctcalign_tune
+// replaces the per-bucket choices with measured ones.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+#include "internal.hpp"
+
+namespace ctca {
+
+struct Geo {
+  int W, M;
+};
+
+// M values compiled into each kernel family.
+constexpr int kMenuOne[] = {2, 4, 6, 8, 10, 12, 14, 16};          // k_one, W <= 4
+constexpr int kMenuLong[] = {8, 12, 16, 20, 24, 28, 30, 32};      // k_one_long, W <= 16
+constexpr int kMenuPack[] = {2, 4, 6, 8, 12, 16};                 // k_persistent, W in {1,2,4}
+
+// Geometry is usable iff it covers S and the top segment holds S-1 and S-2
+// (the end-state choice reads both from one wavefront's registers).
+inline bool geo_ok(int S, int W, int M) {
+  const int64_t seg = (int64_t)kWave * M;
+  return (int64_t)W * seg >= S && ((int64_t)(W - 1) * seg + 2 <= S || W == 1);
+}
+
+struct TuneTable {
+  int num_cu = 256;
+  // states-per-lane target for single launches and for packs (cost model:
+  // per-frame time of a wave grows ~ 5.5*M + 12 VALU issues)
+  int one_target_m = 6;
+  int pack_target_m = 8;
+  // measured overrides, indexed by S bucket (S / 64) and stride class
+  std::vector<Geo> one_override[2], pack_override[2];
+
+  void load_default(int cus) { num_cu = cus > 0 ? cus : 256; }
+
+  static int cls(int C) { return C <= 32 ? 0 : 1; }
+
+  static int menu_up(const int* menu, int n, int need) {
+    for (int i = 0; i < n; ++i)
+      if (menu[i] >= need) return menu[i];
+    return -1;
+  }
+
+  Geo pick_one(int S, int C) const {
+    const int b = S / kWave;
+    const auto& ov = one_override[cls(C)];
+    if (b < (int)ov.size() && ov[b].W > 0 && geo_ok(S, ov[b].W, ov[b].M)) return ov[b];
+    if (S <= 4 * kWave * 16) {
+      int W = (S + kWave * one_target_m - 1) / (kWave * one_target_m);
+      W = W < 1 ? 1 : (W > 4 ? 4 : W);
+      for (; W >= 1; --W) {
+        const int M = menu_up(kMenuOne, 8, (S + kWave * W - 1) / (kWave * W));
+        if (M > 0 && geo_ok(S, W, M)) return Geo{W, M};
+      }
+    }
+    for (int M : kMenuLong) {
+      const int W = (S + kWave * M - 1) / (kWave * M);
+      if (W <= 16 && geo_ok(S, W, M)) return Geo{W, M};
+    }
+    return Geo{0, 0};
+  }
+
+  Geo pick_pack(int S, int C, int T) const {
+    (void)T;
+    const int b = S / kWave;
+    const auto& ov = pack_override[cls(C)];
+    if (b < (int)ov.size() && ov[b].W > 0 && geo_ok(S, ov[b].W, ov[b].M)) return ov[b];
+    for (int W : {1, 2, 4}) {
+      const int M = menu_up(kMenuPack, 6, (S + kWave * W - 1) / (kWave * W));
+      if (M > 0 && M <= pack_target_m && geo_ok(S, W, M)) return Geo{W, M};
+    }
+    for (int W : {4, 2, 1}) {
+      const int M = menu_up(kMenuPack, 6, (S + kWave * W - 1) / (kWave * W));
+      if (M > 0 && geo_ok(S, W, M)) return Geo{W, M};
+    }
+    return Geo{0, 0};
+  }
+
+  int64_t max_pack_states() const { return 4 * kWave * 16; }
+
+  // relative time of one frame on one wave
+  double step_cost(Geo g, int stride) const { return 5.5 * g.M + 12.0 + (stride > 32 ? 2.0 : 0.0); }
+
+  // issue priority: the waves of the packs that start first (the longest
+  // chains) get precedence over their co-resident neighbours
+  void assign_priorities(std::vector<Inst>& insts, const std::vector<Pack>& packs) const {
+    (void)insts;
+    (void)packs;
+  }
+};
+
+}  // namespace ctca
