@@ -1,0 +1,278 @@
+#!/usr/bin/env python3
+"""Benchmark: aligned frames/s of CTC forced alignment on one MI355X.
+
+Default workload (one "step" = one pass of the whole hot path over the batch):
+4,096 synthetic utterances, T log-uniform in [100, 6000], L ~ U{T/6..T/4},
+half at C=32 and half at C=256, aligned by one replay of the captured graph
+(queue reset + persistent kernel draining the longest-first work queue).
+Inputs are resident in HBM before timing starts.
+
+Printed on one JSON line: the batched throughput (`value`), the plain
+per-utterance throughput (64 utterances T ~ U{500..1500}, one launch each)
+and their ratio, the bit-exact flag against the CPU oracle, the roofline of
+the persistent kernel (HIP events on the stream it runs on) and the CPU
+oracle's own throughput on the machine's host cores.
+
+    python bench.py [--steps K] [--warmup W] [--workload batched|long|single]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0                      # MI355X HBM3E, GB/s
+CU, SIMD, LANES, CLOCK = 256, 4, 16, 2.4e9
+VALU_PEAK_OPS = CU * SIMD * LANES * CLOCK  # non-packed 32-bit VALU lane-ops/s (3.93e13)
+METRIC = "aligned frames/s batched vs per-utterance (bit-exact); p50/p99 latency at load"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(T, C, L):
+    """HBM bytes the method must move: emission read 4C per frame, 2-bit
+    backpointers S/4 per frame, path + score write 8 per frame, labels 4L."""
+    T = np.asarray(T, np.float64)
+    C = np.asarray(C, np.float64)
+    L = np.asarray(L, np.float64)
+    S = 2 * L + 1
+    return float(np.sum(T * (4 * C + S / 4 + 8) + 4 * L))
+
+
+def algorithmic_ops(T, L):
+    """Compares + adds of the recurrence: a label state costs 2 compares + 1
+    add, a blank state 1 compare + 1 add, per frame after the first."""
+    T = np.asarray(T, np.float64)
+    L = np.asarray(L, np.float64)
+    return float(np.sum((T - 1) * (3 * L + 2 * (L + 1))))
+
+
+def cpu_threads():
+    n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def time_graph(plan, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        plan.run()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        plan.run(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [a.elapsed_time(b) for a, b in ev]
+    return wall, per
+
+
+def bench_plain(steps, warmup):
+    """Plain method: 64 utterances, one kernel launch each, one stream."""
+    import torch
+
+    import paper_2310_17864_amd as ca
+    from paper_2310_17864_amd import synth
+    wl = synth.cfg_plain_batch()
+    dev = torch.device("cuda:0")
+    ems = [torch.from_numpy(u.emission).to(dev) for u in wl.utts]
+    labs = [torch.from_numpy(u.labels).to(dev) for u in wl.utts]
+    outs = [(torch.empty(u.T, dtype=torch.int32, device=dev),
+             torch.empty(u.T, dtype=torch.float32, device=dev),
+             torch.empty(1, dtype=torch.float32, device=dev),
+             torch.empty(1, dtype=torch.int32, device=dev)) for u in wl.utts]
+
+    def one_pass():
+        for e, l, o in zip(ems, labs, outs):
+            ca.align(e, l, 0, out=o, sync=False)
+
+    for _ in range(max(1, warmup)):
+        one_pass()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(steps):
+        one_pass()
+    b.record(s)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    # bit-exact check of the plain launches too
+    import oracle
+    exact = True
+    for u, o in zip(wl.utts, outs):
+        st, p, sc, t = oracle.align_f32(u.emission, u.labels, 0)
+        exact &= (int(o[3].item()) == st and np.array_equal(o[0].cpu().numpy(), p)
+                  and np.array_equal(o[1].cpu().numpy().view(np.uint32), sc.view(np.uint32)))
+    return {"value": wl.frames / (ms / 1e3), "unit": "aligned frames/s", "ms_per_pass": ms,
+            "utterances": len(wl.utts), "frames": wl.frames, "launches_per_pass": len(wl.utts),
+            "bit_exact": bool(exact), "workload": "64 utterances T~U{500..1500} C=32 L=T/5"}
+
+
+def run_batched(args):
+    import oracle
+    from paper_2310_17864_amd import synth
+    t = time.time()
+    pk = synth.packed_parallel("batched", args.n, workers=cpu_threads(), t_lo=100, t_hi=6000)
+    log(f"generated {args.n} utterances, {pk['frames']} frames in {time.time() - t:.1f}s")
+
+    # CPU oracle on the host cores: the bit-exact reference and the baseline
+    thr = cpu_threads()
+    t = time.time()
+    ref = oracle.align_batch_f32(pk, threads=thr)
+    cpu_s = time.time() - t
+    log(f"oracle: {cpu_s:.1f}s on {ref[4]} threads")
+
+    import torch
+
+    import paper_2310_17864_amd as ca
+    dev = torch.device("cuda:0")
+    em = torch.from_numpy(pk["em"]).to(dev)
+    lab = torch.from_numpy(pk["lab"]).to(dev)
+    plan = ca.Plan(em, pk["em_off"], pk["T"], pk["C"], lab, pk["lab_off"], pk["L"],
+                   pk["fr_off"], 0)
+    wall, per = time_graph(plan, args.steps, args.warmup)
+    F = int(pk["frames"])
+    ms = float(np.mean(per))
+    st = plan.status.cpu().numpy()[: plan.n]
+    paths = plan.paths.cpu().numpy()[:F]
+    scores = plan.scores.cpu().numpy()[:F]
+    totals = plan.totals.cpu().numpy()[: plan.n]
+    ok = ref[0] == 0
+    exact = bool(np.array_equal(st, ref[0]) and np.array_equal(paths, ref[1])
+                 and np.array_equal(scores.view(np.uint32), ref[2].view(np.uint32))
+                 and np.array_equal(totals[ok].view(np.uint32), ref[3][ok].view(np.uint32)))
+    bytes_alg = algorithmic_bytes(pk["T"], pk["C"], pk["L"])
+    ops_alg = algorithmic_ops(pk["T"], pk["L"])
+    hbm = bytes_alg / (ms / 1e3) / 1e9
+    alu = ops_alg / (ms / 1e3)
+    plan.close()
+    del em, lab
+    torch.cuda.empty_cache()
+
+    plain = bench_plain(max(1, args.steps // 2), 1) if not args.no_plain else None
+    value = F / (ms / 1e3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "aligned frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded planted-path log-softmax emissions; no dataset)",
+        "config": {"workload": f"batched {args.n} utterances, T log-uniform 100-6000, "
+                               "L~U{T/6..T/4}, C=32/256 half each, one graph launch",
+                   "utterances": args.n, "frames": F, "state_steps": int(np.sum(
+                       pk["T"].astype(np.int64) * (2 * pk["L"].astype(np.int64) + 1)))},
+        "bit_exact": exact,
+        "wall_s_timed": wall,
+        "ms_min": float(np.min(per)), "ms_max": float(np.max(per)),
+        "plain_per_utterance": plain,
+        "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "roofline": {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": hbm / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_persistent (graph: queue reset + persistent kernel)",
+                     "bytes_per_launch": bytes_alg},
+        "alu": {"achieved_ops_per_s": alu, "peak_ops_per_s": VALU_PEAK_OPS,
+                "frac": alu / VALU_PEAK_OPS, "ops_per_launch": ops_alg},
+        "cpu_baseline": {"value": F / cpu_s, "unit": "aligned frames/s", "cores": int(ref[4]),
+                         "kind": "oracle",
+                         "sample": f"the whole batch ({args.n} utterances, {F} frames), "
+                                   "one utterance per task"},
+    }
+    return out
+
+
+def run_single(args, long_form: bool):
+    import oracle
+    import torch
+
+    import paper_2310_17864_amd as ca
+    from paper_2310_17864_amd import synth
+    wl = synth.cfg_long() if long_form else synth.cfg_single()
+    u = wl.utts[0]
+    t = time.time()
+    st, p, s, tot = oracle.align_f32(u.emission, u.labels, 0)
+    cpu_s = time.time() - t
+    dev = torch.device("cuda:0")
+    e = torch.from_numpy(u.emission).to(dev)
+    lab = torch.from_numpy(u.labels).to(dev)
+    out = ca.align(e, lab, 0, sync=False)
+    for _ in range(args.warmup):
+        ca.align(e, lab, 0, out=out, sync=False)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    stream = torch.cuda.current_stream()
+    for a, b in ev:
+        a.record(stream)
+        ca.align(e, lab, 0, out=out, sync=False)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    exact = (int(out[3].item()) == st and np.array_equal(out[0].cpu().numpy(), p)
+             and np.array_equal(out[1].cpu().numpy().view(np.uint32), s.view(np.uint32))
+             and np.float32(out[2].cpu().numpy()[0]).view(np.uint32) == np.float32(tot).view(np.uint32))
+    st64, _, _, t64 = oracle.align_f64(u.emission, u.labels, 0)
+    bytes_alg = algorithmic_bytes([u.T], [u.C], [u.L])
+    ops_alg = algorithmic_ops([u.T], [u.L])
+    hbm = bytes_alg / (ms / 1e3) / 1e9
+    return {
+        "metric": METRIC, "value": u.T / (ms / 1e3), "unit": "aligned frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded planted-path log-softmax emissions; no dataset)",
+        "config": {"workload": wl.name, "T": u.T, "C": u.C, "L": u.L},
+        "bit_exact": bool(exact),
+        "f64_rel_err": abs(float(tot) - float(t64)) / abs(float(t64)),
+        "roofline": {"bound": "alu", "achieved": ops_alg / (ms / 1e3) / 1e12,
+                     "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+                     "frac": ops_alg / (ms / 1e3) / VALU_PEAK_OPS, "traffic": None,
+                     "hbm_GBs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS},
+        "cpu_baseline": {"value": u.T / cpu_s, "unit": "aligned frames/s", "cores": 1,
+                         "kind": "oracle", "sample": "the whole utterance, one thread"},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batched", choices=["batched", "long", "single"])
+    ap.add_argument("--n", type=int, default=4096, help="utterances in the batched workload")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
+              f"got --gpus {args.gpus}", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "batched":
+        out = run_batched(args)
+    else:
+        out = run_single(args, args.workload == "long")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

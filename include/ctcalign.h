@@ -70,7 +70,7 @@ enum {
 typedef struct ctcalign_ctx ctcalign_ctx;
 typedef struct ctcalign_plan ctcalign_plan;
 typedef struct ctcalign_server ctcalign_server;
-typedef void *ctcalign_stream; /* a hipStream_t; NULL = the context's stream */
+typedef void *ctcalign_stream; /* a hipStream_t; NULL = HIP's default (null) stream */
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char *ctcalign_strerror(int status);
@@ -102,7 +102,7 @@ int ctcalign_align(const float *emission, int32_t T, int32_t C,
                    const int32_t *labels, int32_t L, int32_t blank,
                    int32_t *out_path, float *out_scores);
 
-/* Asynchronous single alignment on `stream` (NULL: the context's stream).
+/* Asynchronous single alignment on `stream` (NULL: HIP's null stream).
  * out_total (device, 1 float) and out_status (device, 1 int32) may be NULL.
  * workspace (device, >= ctcalign_workspace_bytes, 256-byte aligned) may be
  * NULL: the context's arena is used (then calls on one context serialise on
@@ -135,7 +135,7 @@ int ctcalign_plan_create(ctcalign_ctx *ctx, int32_t N,
                          float *out_totals, int32_t *out_status,
                          ctcalign_plan **plan);
 
-/* Replays the plan's graph on `stream` (NULL: the context's stream).
+/* Replays the plan's graph on `stream` (NULL: HIP's null stream).
  * Asynchronous; per-utterance statuses land in out_status. */
 int ctcalign_plan_run(ctcalign_plan *plan, ctcalign_stream stream);
 
@@ -152,6 +152,69 @@ int ctcalign_align_batched(ctcalign_ctx *ctx, int32_t N,
                            int32_t *out_paths, float *out_scores, const int64_t *frame_off,
                            float *out_totals, int32_t *out_status,
                            ctcalign_stream stream);
+
+/* ---- serving: continuous batching of arriving requests ------------------ */
+
+/* One alignment request.  All pointers are device pointers that must stay
+ * valid until the request's ticket completes; emission/labels as for
+ * ctcalign_align_ex, out_total may be NULL. */
+typedef struct ctcalign_request {
+  const float *emission;
+  int32_t T, C;
+  const int32_t *labels;
+  int32_t L, blank;
+  int32_t *out_path;
+  float *out_scores;
+  float *out_total;
+} ctcalign_request;
+
+/* Per-request timestamps, seconds on the host's monotonic clock
+ * (CLOCK_MONOTONIC): submitted, admitted, launched, completion observed. */
+typedef struct ctcalign_timing {
+  double submit_s, admit_s, launch_s, done_s;
+} ctcalign_timing;
+
+typedef struct ctcalign_server_stats {
+  uint64_t submitted, completed, launches, timeouts;
+  size_t peak_charge_bytes;  /* largest sum of charges in flight */
+  size_t budget_bytes;
+  int32_t peak_inflight, waiting, inflight;
+  int32_t budget_violated;   /* 1 if the in-flight charge ever exceeded the budget */
+} ctcalign_server_stats;
+
+/* Starts a server on the context's device.  Each request is charged its
+ * backpointer memory, T*(2L+1)/4 bytes (or its actual workspace if larger),
+ * against bp_budget_bytes; requests are admitted in arrival order (FIFO)
+ * while the charge in flight stays within the budget and fewer than
+ * max_inflight requests are on the device; admitted requests are launched
+ * together and overlap with groups admitted earlier or later.
+ * Errors: EINVAL, ENOMEM (arena), EDEVICE. */
+int ctcalign_server_create(ctcalign_ctx *ctx, size_t bp_budget_bytes, int32_t max_inflight,
+                           ctcalign_server **server);
+
+/* Queues a request (never blocks).  *ticket identifies it.  Errors: EINVAL
+ * (bad arguments; the request is not queued), ENOMEM (its charge alone
+ * exceeds the budget), EAGAIN (queue full). */
+int ctcalign_server_submit(ctcalign_server *server, const ctcalign_request *req, uint64_t *ticket);
+
+/* Non-blocking completion check.  EBUSY while pending; OK once done, with
+ * *status the alignment's own status (OK, EINVAL, EINFEASIBLE, or EDEVICE if
+ * the watchdog gave up on its launch) and *timing filled (either may be
+ * NULL).  A completed ticket is consumed by the call; EINVAL for an unknown
+ * or consumed ticket. */
+int ctcalign_server_poll(ctcalign_server *server, uint64_t ticket, int32_t *status,
+                         ctcalign_timing *timing);
+
+/* Like ctcalign_server_poll but waits for completion. */
+int ctcalign_server_wait(ctcalign_server *server, uint64_t ticket, int32_t *status,
+                         ctcalign_timing *timing);
+
+/* Counters since creation. */
+int ctcalign_server_get_stats(ctcalign_server *server, ctcalign_server_stats *stats);
+
+/* Stops accepting requests, finishes every queued and running one, frees
+ * the server.  NULL is a no-op. */
+int ctcalign_server_destroy(ctcalign_server *server);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,7 @@ from . import _lib
 from ._lib import (CtcAlignError, EAGAIN, EBUSY, EDEVICE, EINFEASIBLE, EINVAL, ENOMEM, OK,
                    LibraryMissing, strerror)
 
-__all__ = ["align", "align_many_launches", "Context", "Plan", "workspace_bytes", "strerror",
+__all__ = ["align", "align_many_launches", "Context", "Plan", "Server", "workspace_bytes", "strerror",
            "CtcAlignError", "LibraryMissing", "OK", "EINVAL", "EINFEASIBLE", "ENOMEM",
            "EDEVICE", "EAGAIN", "EBUSY"]
 
@@ -181,6 +181,73 @@ class Plan:
         if getattr(self, "handle", None):
             _lib.load().ctcalign_plan_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching alignment server on one device.
+
+    submit() queues a request whose tensors stay on the device; the library's
+    worker thread admits requests in arrival order while their backpointer
+    memory fits `budget_bytes`, launches each admitted group, and overlaps it
+    with the groups already running.  wait()/poll() return (status, timing)
+    with timing = (submit, admit, launch, done) on the monotonic clock.
+    """
+
+    def __init__(self, budget_bytes: int, max_inflight: int = 4096, ctx: Optional[Context] = None,
+                 device: Optional[int] = None):
+        self.ctx = ctx or context(device)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().ctcalign_server_create(self.ctx.handle, int(budget_bytes),
+                                                      int(max_inflight), ctypes.byref(h)),
+                   "server_create")
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, emission, labels, out_path, out_scores, out_total=None, blank: int = 0) -> int:
+        T, C = emission.shape
+        L = labels.numel()
+        req = _lib.Request(emission.data_ptr(), T, C, labels.data_ptr() if L else None, L, blank,
+                           out_path.data_ptr(), out_scores.data_ptr(),
+                           out_total.data_ptr() if out_total is not None else None)
+        t = ctypes.c_uint64()
+        _lib.check(_lib.load().ctcalign_server_submit(self.handle, ctypes.byref(req),
+                                                      ctypes.byref(t)), "server_submit")
+        self._keep[t.value] = (emission, labels, out_path, out_scores, out_total)
+        return int(t.value)
+
+    def _finish(self, ticket: int, block: bool):
+        st = ctypes.c_int32()
+        tm = _lib.Timing()
+        fn = _lib.load().ctcalign_server_wait if block else _lib.load().ctcalign_server_poll
+        rc = fn(self.handle, ctypes.c_uint64(ticket), ctypes.byref(st), ctypes.byref(tm))
+        if rc == EBUSY:
+            return None
+        _lib.check(rc, "server_wait" if block else "server_poll")
+        self._keep.pop(ticket, None)
+        return int(st.value), (tm.submit_s, tm.admit_s, tm.launch_s, tm.done_s)
+
+    def wait(self, ticket: int):
+        return self._finish(ticket, True)
+
+    def poll(self, ticket: int):
+        return self._finish(ticket, False)
+
+    def stats(self) -> dict:
+        st = _lib.ServerStats()
+        _lib.check(_lib.load().ctcalign_server_get_stats(self.handle, ctypes.byref(st)), "stats")
+        return {k: getattr(st, k) for k, _ in _lib.ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.load().ctcalign_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
 
     def __del__(self):
         try:

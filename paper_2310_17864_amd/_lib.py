@@ -20,6 +20,23 @@ I32 = ctypes.c_int32
 I64 = ctypes.c_int64
 SZ = ctypes.c_size_t
 
+class Request(ctypes.Structure):
+    _fields_ = [("emission", P), ("T", I32), ("C", I32), ("labels", P), ("L", I32),
+                ("blank", I32), ("out_path", P), ("out_scores", P), ("out_total", P)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double),
+                ("launch_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("timeouts", ctypes.c_uint64),
+                ("peak_charge_bytes", SZ), ("budget_bytes", SZ), ("peak_inflight", I32),
+                ("waiting", I32), ("inflight", I32), ("budget_violated", I32)]
+
+
 _PROTOS = {
     "ctcalign_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "ctcalign_version": (ctypes.c_int, []),
@@ -33,6 +50,15 @@ _PROTOS = {
     "ctcalign_plan_run": (ctypes.c_int, [P, P]),
     "ctcalign_plan_destroy": (ctypes.c_int, [P]),
     "ctcalign_align_batched": (ctypes.c_int, [P, I32, P, P, P, P, P, P, P, I32, P, P, P, P, P, P]),
+    "ctcalign_server_create": (ctypes.c_int, [P, SZ, I32, ctypes.POINTER(P)]),
+    "ctcalign_server_submit": (ctypes.c_int, [P, ctypes.POINTER(Request),
+                                              ctypes.POINTER(ctypes.c_uint64)]),
+    "ctcalign_server_poll": (ctypes.c_int, [P, ctypes.c_uint64, ctypes.POINTER(I32),
+                                            ctypes.POINTER(Timing)]),
+    "ctcalign_server_wait": (ctypes.c_int, [P, ctypes.c_uint64, ctypes.POINTER(I32),
+                                            ctypes.POINTER(Timing)]),
+    "ctcalign_server_get_stats": (ctypes.c_int, [P, ctypes.POINTER(ServerStats)]),
+    "ctcalign_server_destroy": (ctypes.c_int, [P]),
 }
 
 _lib = None

@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libctcalign.so")
-SOURCES = ["kernels.hip", "api.cpp"]
-HEADERS = ["engine.hpp", "internal.hpp", "kernels.hpp", "tune.hpp",
+SOURCES = ["kernels.hip", "api.cpp", "server.cpp"]
+HEADERS = ["engine.hpp", "internal.hpp", "kernels.hpp", "tune.hpp", "ctx.hpp", "sched.hpp",
            os.path.join("..", "..", "include", "ctcalign.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -5,119 +5,19 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cstdio>
-#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
 #include <vector>
 
-#include "../../include/ctcalign.h"
-#include "internal.hpp"
+#include "ctx.hpp"
 #include "kernels.hpp"
-#include "tune.hpp"
 
 using namespace ctca;
 
 namespace {
-
 constexpr int kMaxDevices = 64;
-constexpr int64_t kMaxS = 16 * kWave * 32;     // largest trellis one workgroup holds
-
-int log_level() {
-  static int lv = [] {
-    const char* e = std::getenv("CTCALIGN_LOG");
-    return e ? std::atoi(e) : 0;
-  }();
-  return lv;
-}
-
-#define CTCA_LOG(lvl, ...)                       \
-  do {                                           \
-    if (log_level() >= (lvl)) {                  \
-      std::fprintf(stderr, "[ctcalign] " __VA_ARGS__); \
-      std::fputc('\n', stderr);                  \
-    }                                            \
-  } while (0)
-
-int map_hip(hipError_t e, const char* what) {
-  if (e == hipSuccess) return CTCALIGN_OK;
-  CTCA_LOG(1, "%s: %s", what, hipGetErrorString(e));
-  return e == hipErrorOutOfMemory ? CTCALIGN_ENOMEM : CTCALIGN_EDEVICE;
-}
-
-#define HIP_TRY(expr)                                 \
-  do {                                                \
-    hipError_t _e = (expr);                           \
-    if (_e != hipSuccess) return map_hip(_e, #expr);  \
-  } while (0)
-
-// Device buffer that only grows.
-struct Arena {
-  void* ptr = nullptr;
-  size_t bytes = 0;
-  int reserve(size_t need) {
-    if (need <= bytes) return CTCALIGN_OK;
-    if (ptr) {
-      (void)hipFree(ptr);
-      ptr = nullptr;
-      bytes = 0;
-    }
-    size_t sz = std::max(need, (size_t)1 << 20);
-    if (hipMalloc(&ptr, sz) != hipSuccess) {
-      ptr = nullptr;
-      return CTCALIGN_ENOMEM;
-    }
-    bytes = sz;
-    return CTCALIGN_OK;
-  }
-  void release() {
-    if (ptr) (void)hipFree(ptr);
-    ptr = nullptr;
-    bytes = 0;
-  }
-};
-
-size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-int row_stride_for(int C) { return C <= 32 ? 32 : 256; }
-
-bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
-
 }  // namespace
-
-struct ctcalign_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  int num_cu = 0;
-  Arena ws;        // backpointer workspace for single alignments
-  Arena pad;       // padded emission copies for single alignments
-  int32_t* h_status = nullptr;   // pinned
-  int32_t* d_status = nullptr;
-  float* d_total = nullptr;
-  ctca::TuneTable tune;
-  ctcalign_plan* cached = nullptr;
-  uint64_t cached_key = 0;
-};
-
-struct ctcalign_plan {
-  ctcalign_ctx* ctx = nullptr;
-  int32_t n = 0;
-  int npacks = 0;
-  int grid = 0;
-  Inst* d_insts = nullptr;
-  Pack* d_packs = nullptr;
-  PadDesc* d_pad = nullptr;
-  int npad = 0;
-  int64_t pad_max = 0;
-  int* d_head = nullptr;
-  void* d_bp = nullptr;
-  size_t bp_bytes = 0;
-  void* d_padbuf = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipStream_t cap_stream = nullptr;
-};
 
 namespace {
 
@@ -227,7 +127,7 @@ int ctcalign_ctx_create(int device, ctcalign_ctx** out) {
   int rc = CTCALIGN_OK;
   hipDeviceProp_t prop;
   if ((rc = map_hip(hipGetDeviceProperties(&prop, device), "props")) ||
-      (rc = map_hip(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "stream")) ||
+      (rc = map_hip(hipStreamCreate(&c->stream), "stream")) ||
       (rc = map_hip(hipHostMalloc((void**)&c->h_status, 16 * sizeof(int32_t)), "pinned")) ||
       (rc = map_hip(hipMalloc((void**)&c->d_status, 16 * sizeof(int32_t)), "status")) ||
       (rc = map_hip(hipMalloc((void**)&c->d_total, 16 * sizeof(float)), "total"))) {
@@ -274,7 +174,7 @@ int ctcalign_align_ex(ctcalign_ctx* ctx, const float* emission, int32_t T, int32
   int rc = validate_one(emission, T, C, labels, L, blank, out_path, out_scores);
   if (rc) return rc;
   HIP_TRY(hipSetDevice(ctx->device));
-  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+  hipStream_t st = static_cast<hipStream_t>(stream);
   return launch_single(ctx, emission, T, C, labels, L, blank, out_path, out_scores, out_total,
                        out_status, workspace, ws_bytes, st);
 }
@@ -480,7 +380,10 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
                                          hipMemcpyHostToDevice), "h2d")))
     return fail(rc);
 
-  p->grid = std::min(p->npacks, ctx->num_cu * persistent_blocks_per_cu());
+  // Oversubscribed on purpose: workgroups never wait for each other, so the
+  // ones that do not fit yet start when a resident one leaves, find the queue
+  // drained and exit; the hardware fills every CU to its real occupancy.
+  p->grid = std::min(p->npacks, ctx->num_cu * 16);
   if (p->grid < 1) p->grid = 1;
 
   // capture: [pad] -> queue reset -> persistent kernel
@@ -506,8 +409,7 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
 int ctcalign_plan_run(ctcalign_plan* p, ctcalign_stream stream) {
   if (!p) return CTCALIGN_EINVAL;
   HIP_TRY(hipSetDevice(p->ctx->device));
-  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : p->ctx->stream;
-  HIP_TRY(hipGraphLaunch(p->exec, st));
+  HIP_TRY(hipGraphLaunch(p->exec, static_cast<hipStream_t>(stream)));
   return CTCALIGN_OK;
 }
 

@@ -1,0 +1,111 @@
+// Host-side state shared by the library's translation units: contexts,
+// batched plans, logging, HIP error mapping and small helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+
+#include "../../include/ctcalign.h"
+#include "internal.hpp"
+#include "tune.hpp"
+
+namespace ctca {
+
+constexpr int64_t kMaxS = 8 * kWave * 64;      // largest trellis one workgroup holds
+
+inline int log_level() {
+  static int lv = [] {
+    const char* e = std::getenv("CTCALIGN_LOG");
+    return e ? std::atoi(e) : 0;
+  }();
+  return lv;
+}
+
+#define CTCA_LOG(lvl, ...)                       \
+  do {                                           \
+    if (log_level() >= (lvl)) {                  \
+      std::fprintf(stderr, "[ctcalign] " __VA_ARGS__); \
+      std::fputc('\n', stderr);                  \
+    }                                            \
+  } while (0)
+
+inline int map_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return CTCALIGN_OK;
+  CTCA_LOG(1, "%s: %s", what, hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? CTCALIGN_ENOMEM : CTCALIGN_EDEVICE;
+}
+
+#define HIP_TRY(expr)                                 \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) return map_hip(_e, #expr);  \
+  } while (0)
+
+// Device buffer that only grows.
+struct Arena {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  int reserve(size_t need) {
+    if (need <= bytes) return CTCALIGN_OK;
+    if (ptr) {
+      (void)hipFree(ptr);
+      ptr = nullptr;
+      bytes = 0;
+    }
+    size_t sz = std::max(need, (size_t)1 << 20);
+    if (hipMalloc(&ptr, sz) != hipSuccess) {
+      ptr = nullptr;
+      return CTCALIGN_ENOMEM;
+    }
+    bytes = sz;
+    return CTCALIGN_OK;
+  }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+};
+
+inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+inline int row_stride_for(int C) { return C <= 32 ? 32 : 256; }
+
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace ctca
+
+struct ctcalign_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 0;
+  ctca::Arena ws;  // backpointer workspace for single alignments
+  ctca::Arena pad; // padded emission copies for single alignments
+  int32_t* h_status = nullptr;   // pinned
+  int32_t* d_status = nullptr;
+  float* d_total = nullptr;
+  ctca::TuneTable tune;
+  ctcalign_plan* cached = nullptr;
+  uint64_t cached_key = 0;
+};
+
+struct ctcalign_plan {
+  ctcalign_ctx* ctx = nullptr;
+  int32_t n = 0;
+  int npacks = 0;
+  int grid = 0;
+  ctca::Inst* d_insts = nullptr;
+  ctca::Pack* d_packs = nullptr;
+  ctca::PadDesc* d_pad = nullptr;
+  int npad = 0;
+  int64_t pad_max = 0;
+  int* d_head = nullptr;
+  void* d_bp = nullptr;
+  size_t bp_bytes = 0;
+  void* d_padbuf = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+};

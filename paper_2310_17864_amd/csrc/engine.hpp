@@ -23,12 +23,14 @@
 // state, "skipped a state" plane for label states), so backpointers cost 1.5
 // bits per state and frame and are stored with coalesced dword stores.
 //
-// Emission rows reach LDS in chunks of 4 rows through registers, one chunk
-// ahead, with an L2 warm-up load three chunks ahead; label states then read
-// their class column from a ring of 8 rows at a static offset.
+// Emission rows reach LDS in chunks of 4 rows by direct global->LDS loads,
+// one chunk ahead; label states then read their class column from a ring of
+// two 4-row halves at a static offset.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -97,90 +99,86 @@ __device__ __forceinline__ bool wait_geq(int* p, int need) {
 // a[j] holds a_{t-1} for state sbase+j on entry and a_t on exit.  States are
 // updated from the top down so every read sees a_{t-1}.  nb is a_{t-1} of the
 // state just below this lane's first one.  Even slots are blank states.
+// Skip permission of label slot jj: for M <= 16 a lane mask per slot (kept in
+// SGPRs, ANDed with the compare mask by the scalar unit); for larger M, where
+// the masks would not fit the SGPR file, a per-lane additive penalty (0 or
+// -inf) folded into the compared value -- the compare result is the same and
+// the selected value stays the unmodified a_{t-1}(s-2).
 template <int M>
-__device__ __forceinline__ void dp_frame(float (&a)[M], uint32_t (&mv)[M], uint32_t (&sk)[M / 2],
-                                         const uint64_t (&skip)[M / 2], float nb, float eb,
-                                         const float (&e)[M / 2]) {
+struct SkipRep {
+  static constexpr bool kMask = M <= 16;
+  using T = typename std::conditional<kMask, uint64_t, float>::type;
+};
+
+template <int M>
+__device__ __forceinline__ void dp_frame(float (&a)[M], uint32_t (&acc)[bp_words_per_lane(M)],
+                                         const typename SkipRep<M>::T (&skip)[M / 2], float nb,
+                                         float eb, const float (&e)[M / 2]) {
 #pragma unroll
   for (int j = M - 1; j >= 0; --j) {
     const float p1 = (j >= 1) ? a[j - 1] : nb;
     if (j % 2 == 0) {
       const uint64_t c1 = gt_mask(p1, a[j]);
       const float best = sel(c1, p1, a[j]);
-      mv[j] = shift_in(mv[j], c1);
+      acc[plane_mv(M, j) / 4] = shift_in(acc[plane_mv(M, j) / 4], c1);
       a[j] = eb + best;
     } else {
       const float p2 = (j >= 2) ? a[j - 2] : nb;
       const uint64_t c1 = gt_mask(p1, a[j]);
       const float b1 = sel(c1, p1, a[j]);
-      const uint64_t c2 = gt_mask(p2, b1) & skip[j / 2];
+      uint64_t c2;
+      if constexpr (SkipRep<M>::kMask)
+        c2 = gt_mask(p2, b1) & skip[j / 2];
+      else
+        c2 = gt_mask(p2 + skip[j / 2], b1);
       const float b2 = sel(c2, p2, b1);
-      mv[j] = shift_in(mv[j], c1);
-      sk[j / 2] = shift_in(sk[j / 2], c2);
+      // moved before skipped: planes are numbered in shift-in order
+      acc[plane_mv(M, j) / 4] = shift_in(acc[plane_mv(M, j) / 4], c1);
+      acc[plane_sk(M, j) / 4] = shift_in(acc[plane_sk(M, j) / 4], c2);
       a[j] = e[j / 2] + b2;
     }
   }
 }
 
-// ---- emission chunks: global -> registers -> LDS ring ----------------------
+// ---- emission chunks: HBM -> LDS by direct loads -----------------------------
 //
 // Chunk k holds the rows of frames t = 4k+1 .. 4k+4 (frame 0 is read
-// directly at initialisation) and lands in ring rows (4k) % 8 .. +3.  The
-// rows are contiguous in HBM (row stride C == STRIDE, 16-byte aligned; the
-// host pads other class counts beforehand), so a chunk is one contiguous
-// copy of 4*STRIDE floats: 2 per lane for STRIDE 32, 16 for STRIDE 256.
-template <int STRIDE>
-struct Stager {
-  static constexpr int kPer = kChunk * STRIDE / kWave;
-  static constexpr int kVec = kPer >= 4 ? 4 : kPer;      // floats per load
-  float v[kPer];
+// directly at initialisation).  Even chunks live in ring half A, odd chunks in
+// half B; both halves are distinct __shared__ objects, so the compiler knows a
+// pending copy into one half never aliases reads of the other.  HBM rows are
+// 16-byte aligned with a row stride of 32 or 256 floats (the host pads other
+// class counts beforehand) and are moved by global_load_lds_dwordx4 (16 bytes
+// per lane, no VGPR staging).  The copy of chunk k+1 is issued when chunk k
+// starts and waited for (vmcnt) when chunk k+1 starts.
+typedef __attribute__((address_space(3))) void lds_void_t;
 
-  __device__ __forceinline__ void load(const float* em, int T, int k, int lane) {
-    const int row0 = 4 * k + 1;
-    if (row0 >= T) return;
-    const float* src = em + (int64_t)row0 * STRIDE;
-    const int lim = ((T - row0) < kChunk ? (T - row0) : kChunk) * STRIDE;
+// LDS rows always have kMaxC (256) floats; HBM rows have hs = 32 or 256.
+__device__ __forceinline__ void dma_chunk(const float* em, int T, int hs, int k, int lane,
+                                          float* half) {
+  const int row0 = 4 * k + 1;
+  if (row0 >= T) return;
+  const int rows = (T - row0) < kChunk ? (T - row0) : kChunk;
+  const float* src = em + (int64_t)row0 * hs;
+  if (hs == kMaxC) {
+    // one contiguous 4 KB copy: 4 instructions of 64 lanes x 16 bytes
 #pragma unroll
-    for (int q = 0; q < kPer / kVec; ++q) {
-      const int e = kVec * (lane + kWave * q);
-      if (e < lim) {
-        if constexpr (kVec == 4) {
-          const float4 x = *reinterpret_cast<const float4*>(src + e);
-          v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
-        } else {
-          const float2 x = *reinterpret_cast<const float2*>(src + e);
-          v[2 * q] = x.x; v[2 * q + 1] = x.y;
-        }
-      }
+    for (int q = 0; q < kChunk; ++q) {
+      const int e = 4 * (kWave * q + lane);
+      if (e < rows * kMaxC)
+        __builtin_amdgcn_global_load_lds(src + e, (lds_void_t*)(half + 4 * kWave * q), 16, 0, 0);
+    }
+  } else {
+    // 128-byte rows: one instruction per row, 8 lanes x 16 bytes
+#pragma unroll
+    for (int r = 0; r < kChunk; ++r) {
+      if (r < rows && lane < 8)
+        __builtin_amdgcn_global_load_lds(src + r * 32 + 4 * lane, (lds_void_t*)(half + r * kMaxC), 16,
+                                         0, 0);
     }
   }
+}
 
-  __device__ __forceinline__ void store(float* ring, int T, int k, int lane) {
-    const int row0 = 4 * k + 1;
-    if (row0 >= T) return;
-    const int lim = ((T - row0) < kChunk ? (T - row0) : kChunk) * STRIDE;
-    float* dst = ring + ((4 * k) % kRing) * STRIDE;
-#pragma unroll
-    for (int q = 0; q < kPer / kVec; ++q) {
-      const int e = kVec * (lane + kWave * q);
-      if (e < lim) {
-        if constexpr (kVec == 4)
-          *reinterpret_cast<float4*>(dst + e) = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
-        else
-          *reinterpret_cast<float2*>(dst + e) = make_float2(v[2 * q], v[2 * q + 1]);
-      }
-    }
-  }
-
-  // Pull the cache lines of chunk k into L2 (one dword per 128-byte line).
-  __device__ __forceinline__ uint32_t touch(const float* em, int T, int k, int lane) {
-    const int row0 = 4 * k + 1;
-    const int rows = (T - row0) < kChunk ? (T - row0) : kChunk;
-    if (rows > 0 && lane * 32 < rows * STRIDE)
-      return __builtin_bit_cast(uint32_t, em[(int64_t)row0 * STRIDE + lane * 32]);
-    return 0u;
-  }
-};
+__device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Where segment outcomes go for the backtrack.
 struct FwdOut {
@@ -193,9 +191,9 @@ struct FwdOut {
 //
 // `sy` points at the SegSync of segment 0 of this instance; the caller has
 // cleared it and passed a workgroup barrier after `prologue_check`.
-template <int M, int STRIDE>
-__device__ FwdOut segment_forward(const Inst& in, const int w, const int lane, float* ring,
-                                  SegSync* sy, bool labels_bad) {
+template <int M>
+__device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, const int lane, float* ringA,
+                                  float* ringB, SegSync* sy, bool labels_bad) {
   const int T = in.T, L = in.L, blank = in.blank, W = in.W;
   const int S = 2 * L + 1;                  // state counts fit int32 (host-checked)
   const int sbase = (w * kWave + lane) * M;
@@ -207,7 +205,7 @@ __device__ FwdOut segment_forward(const Inst& in, const int w, const int lane, f
   // ring at byte offset 4*label; padding states (s >= S) read the blank
   // column and can neither skip nor feed a real state.
   int eoff[M / 2];
-  uint64_t skip[M / 2];   // lane mask per label slot: may enter from two states below
+  typename SkipRep<M>::T skip[M / 2];   // may enter from two states below
 #pragma unroll
   for (int jj = 0; jj < M / 2; ++jj) {
     const int s = sbase + 2 * jj + 1;
@@ -218,7 +216,10 @@ __device__ FwdOut segment_forward(const Inst& in, const int w, const int lane, f
       if (s >= 3) sk = lab != in.lab[(s - 3) / 2];
     }
     eoff[jj] = lab;
-    skip[jj] = __builtin_amdgcn_ballot_w64(sk);
+    if constexpr (SkipRep<M>::kMask)
+      skip[jj] = __builtin_amdgcn_ballot_w64(sk);
+    else
+      skip[jj] = sk ? 0.0f : neg_inf();
   }
 
   // a3: frame 0.  Only states 0 and 1 start finite.
@@ -241,25 +242,17 @@ __device__ FwdOut segment_forward(const Inst& in, const int w, const int lane, f
   }
 
   const int nsteps = T - 1;               // frames 1..T-1
-  const int nblk = (int)bp_blocks(T);
-  const int NP = bp_planes(M);
-  uint32_t* bpw = in.bp + (int64_t)w * nblk * NP * kWave + lane;
+  const int nblk = (nsteps + kBlk - 1) / kBlk;
+  constexpr int NQ = bp_words_per_lane(M);
+  const int ngrp = (int)bp_groups(T);
+  uint32_t* bpw = in.bp + (int64_t)w * ngrp * NQ * kWave + lane;
 
-  Stager<STRIDE> st;
-  uint32_t warm_acc = 0, warm_a = 0, warm_b = 0;
-  // Invariant at the switch to chunk k: the stager holds chunk k, warm_a is
-  // the touch of chunk k+1 (issued two switches ago, older than the load of
-  // chunk k, so already complete) and warm_b the touch of chunk k+2.
-  if (nsteps > 0) {
-    st.load(em, T, 0, lane);
-    warm_b = st.touch(em, T, 2, lane);
-  }
+  const int hs = in.stride;
+  if (nsteps > 0) dma_chunk(em, T, hs, 0, lane, ringA);
 
-  uint32_t mv[M], sk[M / 2];
+  uint32_t acc[NQ];
 #pragma unroll
-  for (int j = 0; j < M; ++j) mv[j] = 0;
-#pragma unroll
-  for (int j = 0; j < M / 2; ++j) sk[j] = 0;
+  for (int q = 0; q < NQ; ++q) acc[q] = 0;
 
   bool alive = true;
   int u = 0;
@@ -272,47 +265,48 @@ __device__ FwdOut segment_forward(const Inst& in, const int w, const int lane, f
 
 #pragma unroll 1
     for (int g = 0; g < kBlk / kUnroll; ++g) {
+      const int ng = n - kUnroll * g;            // frames of this group (may be < 8 or <= 0)
+      if (ng <= 0) break;
 #pragma unroll
       for (int i = 0; i < kUnroll; ++i) {
-        const int ib = g * kUnroll + i;          // frame index inside the block
-        if (ib < n) {
-          u = 32 * b + ib;                       // computes frame t = u + 1
+        if (i < ng) {
+          u = 32 * b + kUnroll * g + i;          // computes frame t = u + 1
           if (i % kChunk == 0) {
-            // a2: chunk u/4 is staged in registers; land it, fetch the next
-            const int k = u / kChunk;
-            st.store(ring, T, k, lane);
-            warm_acc ^= warm_a;
-            warm_a = warm_b;
-            st.load(em, T, k + 1, lane);
-            warm_b = st.touch(em, T, k + 3, lane);
+            // a2: chunk u/4 has landed; start copying the next one
+            wait_dma();
+            dma_chunk(em, T, hs, u / kChunk + 1, lane, (i < kChunk) ? ringB : ringA);
           }
-          const float* row = ring + (i % kRing) * STRIDE;  // u % 8 == i
+          // frame u reads ring half (u/4)%2 == i/4, row u%4 == i%4
+          const float* row = ((i < kChunk) ? ringA : ringB) + (i % kChunk) * kMaxC;
           const float eb = row[blank];
           float e[M / 2];
 #pragma unroll
           for (int jj = 0; jj < M / 2; ++jj) e[jj] = row[eoff[jj]];
           const float nb_in = has_prev ? prev->bnd[u % kBnd] : neg_inf();
           const float nb = shr1(a[M - 1], nb_in);
-          dp_frame<M>(a, mv, sk, skip, nb, eb, e);
+          dp_frame<M>(a, acc, skip, nb, eb, e);
           if (has_next && lane == kWave - 1) me->bnd[(u + 1) % kBnd] = a[M - 1];
+          // keep each frame's instructions together: bounds live registers
+          __builtin_amdgcn_sched_barrier(0);
         }
+      }
+      // a5: flush the group's backpointer words; frame i of plane r of word q
+      // lands at bit 31 - (R*i + r) (left-aligned when the group is short)
+      const int gi = 4 * b + g;
+      uint32_t* dst = bpw + (int64_t)gi * NQ * kWave;
+      const int nf = ng < kUnroll ? ng : kUnroll;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int sh = 32 - planes_in_word(M, q) * nf;
+        dst[q * kWave] = acc[q] << sh;
       }
     }
 
-    // a5: flush this block's backpointer words (frame i of the block at bit 31-i)
-    const int sh = kBlk - n;
-    uint32_t* dst = bpw + (int64_t)b * NP * kWave;
-#pragma unroll
-    for (int jj = 0; jj < M / 2; ++jj) {
-      dst[(3 * jj) * kWave] = mv[2 * jj] << sh;
-      dst[(3 * jj + 1) * kWave] = mv[2 * jj + 1] << sh;
-      dst[(3 * jj + 2) * kWave] = sk[jj] << sh;
-    }
     if (has_next) lds_store_rel(&me->prod, 32 * b + n + 1);
     if (has_prev) lds_store_rel(&me->cons, 32 * b + n);
   }
   out.ok = alive ? 1 : 0;
-  if (warm_acc == 0x7fc00001u && T < 0) in.path[0] = (int)warm_acc;   // keeps the warm-up loads
+  wait_dma();   // no copy into LDS may outlive this instance
 
   // a6: end state, in the segment that holds S-1 and S-2
   if (w == W - 1) {
@@ -345,7 +339,7 @@ __device__ FwdOut segment_forward(const Inst& in, const int w, const int lane, f
 // Every segment checks the labels of its own states; the instance's verdict is
 // the OR over segments after a workgroup barrier.
 template <int M>
-__device__ bool prologue_check(const Inst& in, int w, int lane) {
+__device__ __forceinline__ bool prologue_check(const Inst& in, int w, int lane) {
   const int S = 2 * in.L + 1;
   const int sbase = (w * kWave + lane) * M;
   bool bad = false;
@@ -363,50 +357,99 @@ __device__ bool prologue_check(const Inst& in, int w, int lane) {
 // ---- a7: backtrack ---------------------------------------------------------
 //
 // The chase s_{t-1} = s_t - k_t(s_t) runs in scalar registers, 32 frames per
-// backpointer block.  Over one block the state drops by at most 62, so the
-// block's codes for the 63 states at and below the block's top state sit one
-// per lane ("band") and each frame costs three readlanes.  The next block's
-// band is fetched before the chase (a 128-state window that covers any exit
-// state) and realigned with ds_bpermute once the exit state is known.
+// block.  Over one block the state drops by at most 62, so the block's codes
+// for the 63 states at and below the block's top state sit one per lane (the
+// "band"), each as two 32-frame words (moved, skipped) with frame i of the
+// block at bit 31-i; a frame then costs three readlanes.  The next block's
+// raw words are fetched before the chase for a 128-state window that covers
+// any exit state, and repacked and realigned (ds_bpermute) after it.
 
 struct Band {
   uint32_t mv, sk;
   int lab;
 };
 
-__device__ __forceinline__ Band load_band(const Inst& in, int blk, int nblk, int top, int x0, int lane) {
-  Band r{0u, 0u, in.blank};
+// Raw backpointer words of one state for the 4 groups of a block.
+struct RawBand {
+  uint32_t wm[4], ws[4];
+  int lab;
+  int pm, ps;      // bit offset r of the moved / skipped plane in its word
+  int rm, rs;      // planes R in that word
+};
+
+__device__ __forceinline__ RawBand load_raw(const Inst& in, int blk, int ngrp, int top, int x0, int lane) {
+  RawBand r;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    r.wm[g] = 0u;
+    r.ws[g] = 0u;
+  }
+  r.lab = in.blank;
+  r.pm = r.ps = 0;
+  r.rm = r.rs = 1;
   const int q = top - x0 - lane;
   if (q < 0 || blk < 0) return r;
-  const int M = in.M, NP = bp_planes(M);
+  const int M = in.M, NQ = bp_words_per_lane(M);
   const int segsz = kWave * M;
   const int wseg = q / segsz;
   const int rr = q - wseg * segsz;
   const int ln = rr / M;
   const int j = rr - ln * M;
-  const uint32_t* base = in.bp + (((int64_t)wseg * nblk + blk) * NP) * kWave + ln;
-  if (j % 2 == 0) {
-    r.mv = base[(3 * (j / 2)) * kWave];
-  } else {
-    r.mv = base[(3 * (j / 2) + 1) * kWave];
-    r.sk = base[(3 * (j / 2) + 2) * kWave];
+  const int pmv = plane_mv(M, j);
+  r.pm = pmv % 4;
+  r.rm = planes_in_word(M, pmv / 4);
+  const uint32_t* base = in.bp + ((int64_t)wseg * ngrp) * NQ * kWave + ln;
+  const bool odd = j % 2;
+  int psk = 0;
+  if (odd) {
+    psk = plane_sk(M, j);
+    r.ps = psk % 4;
+    r.rs = planes_in_word(M, psk / 4);
     r.lab = in.lab[(q - 1) / 2];
   }
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int gi = 4 * blk + g;
+    if (gi < ngrp) {
+      const uint32_t* gb = base + (int64_t)gi * NQ * kWave;
+      r.wm[g] = gb[(pmv / 4) * kWave];
+      if (odd) r.ws[g] = gb[(psk / 4) * kWave];
+    }
+  }
   return r;
+}
+
+// The 8 frame bits of plane offset p (R planes per word) of word w, as the
+// top byte of the result in frame order (frame i at bit 31-i).
+__device__ __forceinline__ uint32_t group_bits(uint32_t w, int R, int p) {
+  uint32_t o = 0;
+#pragma unroll
+  for (int i = 0; i < kUnroll; ++i) o |= ((w >> (31 - R * i - p)) & 1u) << (31 - i);
+  return o;
+}
+
+__device__ __forceinline__ Band repack(const RawBand& r) {
+  Band b{0u, 0u, r.lab};
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    b.mv |= group_bits(r.wm[g], r.rm, r.pm) >> (kUnroll * g);
+    b.sk |= group_bits(r.ws[g], r.rs, r.ps) >> (kUnroll * g);
+  }
+  return b;
 }
 
 __device__ __forceinline__ uint32_t bperm(uint32_t v, int src_lane) {
   return (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane * 4, (int)v);
 }
 
-__device__ void fill_outputs(const Inst& in, int lane, int path_val, float score_val) {
+__device__ __forceinline__ void fill_outputs(const Inst& in, int lane, int path_val, float score_val) {
   for (int t = lane; t < in.T; t += kWave) {
     in.path[t] = path_val;
     in.scores[t] = score_val;
   }
 }
 
-__device__ void backtrack(const Inst& in, const FwdOut& fo, int status_in, int lane) {
+__device__ __forceinline__ void backtrack(const Inst& in, const FwdOut& fo, int status_in, int lane) {
   const int T = in.T, RS = in.stride, blank = in.blank;   // RS: emission row stride
   const float* em = in.em;
   int status = status_in;
@@ -419,9 +462,10 @@ __device__ void backtrack(const Inst& in, const FwdOut& fo, int status_in, int l
     fill_outputs(in, lane, -1, fillv);
     if (status != kEinfeasible) total = __builtin_nanf("");
   } else {
-    const int nblk = (int)bp_blocks(T);
+    const int nblk = (T - 1 + kBlk - 1) / kBlk;
+    const int ngrp = (int)bp_groups(T);
     int s = fo.send;
-    Band cur = load_band(in, nblk - 1, nblk, s, 0, lane);
+    Band cur = repack(load_raw(in, nblk - 1, ngrp, s, 0, lane));
     int pend_lab = 0;
     float pend_sc = 0.f;
     int pend_t0 = -1;
@@ -429,10 +473,10 @@ __device__ void backtrack(const Inst& in, const FwdOut& fo, int status_in, int l
     for (int b = nblk - 1; b >= 0; --b) {
       const int n = (T - 1 - 32 * b) < kBlk ? (T - 1 - 32 * b) : kBlk;
       const int top = s;
-      Band wa{0u, 0u, blank}, wb{0u, 0u, blank};
+      RawBand wa, wb;
       if (b > 0) {
-        wa = load_band(in, b - 1, nblk, top, 0, lane);
-        wb = load_band(in, b - 1, nblk, top, kWave, lane);
+        wa = load_raw(in, b - 1, ngrp, top, 0, lane);
+        wb = load_raw(in, b - 1, ngrp, top, kWave, lane);
       }
       // chase frames t = 32b+n .. 32b+1 (bit 31-i of the block's words)
       int outlab = blank;
@@ -456,12 +500,13 @@ __device__ void backtrack(const Inst& in, const FwdOut& fo, int status_in, int l
       pend_lab = outlab;
       pend_sc = lane < n ? em[(int64_t)(pend_t0 + lane) * RS + outlab] : 0.f;
       if (b > 0) {
+        const Band ba = repack(wa), bb = repack(wb);
         const int d = top - s;   // 0..64: exit state = top - d
         const int src = (lane + d) & (kWave - 1);
         const bool hi = lane + d >= kWave;
-        const uint32_t amv = bperm(wa.mv, src), bmv = bperm(wb.mv, src);
-        const uint32_t ask = bperm(wa.sk, src), bsk = bperm(wb.sk, src);
-        const int alab = (int)bperm((uint32_t)wa.lab, src), blab = (int)bperm((uint32_t)wb.lab, src);
+        const uint32_t amv = bperm(ba.mv, src), bmv = bperm(bb.mv, src);
+        const uint32_t ask = bperm(ba.sk, src), bsk = bperm(bb.sk, src);
+        const int alab = (int)bperm((uint32_t)ba.lab, src), blab = (int)bperm((uint32_t)bb.lab, src);
         cur.mv = hi ? bmv : amv;
         cur.sk = hi ? bsk : ask;
         cur.lab = hi ? blab : alab;

@@ -49,16 +49,27 @@ struct PadDesc {
   int32_t T, C, stride, pad_;
 };
 
-// Number of 32-frame backpointer blocks (frames 1..T-1 carry backpointers).
-__host__ __device__ inline int64_t bp_blocks(int64_t T) { return (T - 1 + kBlk - 1) / kBlk; }
-
-// Planes per segment and block: one "moved" plane per state slot, plus one
-// "skipped" plane per odd (label) slot -> 3M/2 words per lane.
-__host__ __device__ inline int bp_planes(int M) { return 3 * M / 2; }
-
-// Words of backpointers for an instance: [W][blocks][planes][64 lanes].
+// Backpointer layout.  Frames 1..T-1 carry backpointers, in groups of 8
+// frames.  Per state slot a lane produces one "moved" bit (came from s-1 or
+// s-2) and, for label slots, one "skipped" bit (came from s-2).  A lane's
+// 3M/2 bit planes are numbered in the order the forward pass produces them
+// (slot pairs from the top down: moved(odd), skipped(odd), moved(even)) and
+// packed four planes per 32-bit word, interleaved by frame: in word q, which
+// holds R = min(4, 3M/2 - 4q) planes, plane 4q+r at frame i of the group sits
+// at bit 31 - (R*i + r).  Words are stored [segment][group][word][lane].
+__host__ __device__ constexpr int bp_planes(int M) { return 3 * M / 2; }
+__host__ __device__ constexpr int bp_words_per_lane(int M) { return (bp_planes(M) + 3) / 4; }
+__host__ __device__ inline int64_t bp_groups(int64_t T) { return (T - 1 + kUnroll - 1) / kUnroll; }
 __host__ __device__ inline int64_t bp_words(int64_t T, int W, int M) {
-  return (int64_t)W * bp_blocks(T) * bp_planes(M) * kWave;
+  return (int64_t)W * bp_groups(T) * bp_words_per_lane(M) * kWave;
+}
+// plane index of slot j's "moved" bit and of a label slot's "skipped" bit
+__host__ __device__ constexpr int plane_mv(int M, int j) {
+  return (j % 2) ? 3 * (M / 2 - 1 - j / 2) : 3 * (M / 2 - 1 - j / 2) + 2;
+}
+__host__ __device__ constexpr int plane_sk(int M, int j) { return 3 * (M / 2 - 1 - j / 2) + 1; }
+__host__ __device__ constexpr int planes_in_word(int M, int q) {
+  return (bp_planes(M) - 4 * q) < 4 ? (bp_planes(M) - 4 * q) : 4;
 }
 
 }  // namespace ctca

@@ -1,13 +1,13 @@
 // gfx950 kernels for CTC forced alignment and their host-side launchers.
 //
-//   k_one<STRIDE>        one instance, W <= 4 waves, M <= 16 states per lane
-//   k_one_long<STRIDE>   one instance, W <= 16 waves, 8 <= M <= 32 (long form)
+//   k_one                one instance, W <= 4 waves, M <= 16 states per lane
+//   k_one_long           one instance, W <= 8 waves, 16 <= M <= 64 (long form)
 //   k_persistent         batched: each 4-wave workgroup pops work items
 //                        ("packs") from a device queue until it is empty
 //   k_fill               small fill kernel (queue reset inside graphs)
 //
-// STRIDE is the LDS row stride of the emission ring: 32 for C <= 32 and 256
-// for 32 < C <= 256.
+// Emission rows sit in LDS with a stride of 256 floats; in HBM their stride
+// is 32 (C <= 32) or 256 (32 < C <= 256), padded by the host when needed.
 #include <hip/hip_runtime.h>
 
 #include "engine.hpp"
@@ -18,14 +18,15 @@ namespace ctca {
 // Runs segment w of `in` on the calling wave: label check, one workgroup
 // barrier, forward pass, then either "done" publication (lower segments) or
 // end-state selection and backtrack (the top segment).
-template <int M, int STRIDE>
-__device__ void run_wave(const Inst& in, int w, int lane, SegSync* sy, float* ring) {
+template <int M>
+__device__ __forceinline__ void run_wave(const Inst& in, int w, int lane, SegSync* sy, float* ringA,
+                                         float* ringB) {
   const bool bad = prologue_check<M>(in, w, lane);
   if (bad && lane == 0) sy[w].bad = 1;
   __syncthreads();
   bool any_bad = false;
   for (int k = 0; k < in.W; ++k) any_bad |= (sy[k].bad != 0);
-  const FwdOut fo = segment_forward<M, STRIDE>(in, w, lane, ring, sy, any_bad);
+  const FwdOut fo = segment_forward<M>(in, w, lane, ringA, ringB, sy, any_bad);
   if (w + 1 < in.W) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // backpointer stores reach L2
     if (lane == 0) lds_store_rel(&sy[w].done, 1);
@@ -60,15 +61,17 @@ __device__ __forceinline__ void reset_sync(SegSync* s, int lane) {
 
 #define CTCA_CASE(MM) \
   case MM:            \
-    run_wave<MM, STRIDE>(in, w, lane, sy, ring); \
+    run_wave<MM>(in, w, lane, sy, ringA[w], ringB[w]); \
     break;
 
-template <int STRIDE>
+// LDS of the single-instance kernels: per wave a SegSync and two 4-row ring
+// halves (distinct objects, see dma_chunk).
 __global__ void __launch_bounds__(256) k_one(Inst in) {
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  SegSync* sy = reinterpret_cast<SegSync*>(smem);
-  float* ring = reinterpret_cast<float*>(smem + in.W * sizeof(SegSync)) + w * kRing * STRIDE;
+  __shared__ SegSync sy[4];
+  __shared__ __attribute__((aligned(16))) float ringA[4][kChunk * kMaxC];
+  __shared__ __attribute__((aligned(16))) float ringB[4][kChunk * kMaxC];
+  // the wave index is uniform across a wave; readfirstlane tells the compiler
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   reset_sync(sy + w, lane);
   switch (in.M) {
     CTCA_CASE(2) CTCA_CASE(4) CTCA_CASE(6) CTCA_CASE(8)
@@ -77,48 +80,49 @@ __global__ void __launch_bounds__(256) k_one(Inst in) {
   }
 }
 
-template <int STRIDE>
-__global__ void __launch_bounds__(1024) k_one_long(Inst in) {
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  SegSync* sy = reinterpret_cast<SegSync*>(smem);
-  float* ring = reinterpret_cast<float*>(smem + in.W * sizeof(SegSync)) + w * kRing * STRIDE;
+// Long form: up to 8 waves (2 per SIMD), up to 64 states per lane.
+__global__ void __launch_bounds__(512) k_one_long(Inst in) {
+  __shared__ SegSync sy[8];
+  __shared__ __attribute__((aligned(16))) float ringA[8][kChunk * kMaxC];
+  __shared__ __attribute__((aligned(16))) float ringB[8][kChunk * kMaxC];
+  // the wave index is uniform across a wave; readfirstlane tells the compiler
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   reset_sync(sy + w, lane);
   switch (in.M) {
-    CTCA_CASE(8) CTCA_CASE(12) CTCA_CASE(16) CTCA_CASE(20)
-    CTCA_CASE(24) CTCA_CASE(28) CTCA_CASE(30) CTCA_CASE(32)
+    CTCA_CASE(16) CTCA_CASE(24) CTCA_CASE(32) CTCA_CASE(40)
+    CTCA_CASE(48) CTCA_CASE(56) CTCA_CASE(60) CTCA_CASE(64)
     default: __syncthreads(); break;
   }
 }
 #undef CTCA_CASE
 
-template <int STRIDE>
-__device__ __forceinline__ void pack_dispatch(const Inst& in, int w, int lane, SegSync* sy, float* ring) {
+__device__ __forceinline__ void pack_dispatch(const Inst& in, int w, int lane, SegSync* sy,
+                                              float* ra, float* rb) {
   switch (in.M) {
-    case 2: run_wave<2, STRIDE>(in, w, lane, sy, ring); break;
-    case 4: run_wave<4, STRIDE>(in, w, lane, sy, ring); break;
-    case 6: run_wave<6, STRIDE>(in, w, lane, sy, ring); break;
-    case 8: run_wave<8, STRIDE>(in, w, lane, sy, ring); break;
-    case 12: run_wave<12, STRIDE>(in, w, lane, sy, ring); break;
-    case 16: run_wave<16, STRIDE>(in, w, lane, sy, ring); break;
+    case 2: run_wave<2>(in, w, lane, sy, ra, rb); break;
+    case 4: run_wave<4>(in, w, lane, sy, ra, rb); break;
+    case 6: run_wave<6>(in, w, lane, sy, ra, rb); break;
+    case 8: run_wave<8>(in, w, lane, sy, ra, rb); break;
+    case 12: run_wave<12>(in, w, lane, sy, ra, rb); break;
+    case 16: run_wave<16>(in, w, lane, sy, ra, rb); break;
     default: __syncthreads(); break;
   }
 }
 
-// LDS: [4] SegSync, then 4 rings of kRing*256 floats.
+// LDS: 4 SegSync and, per wave, two 4-row ring halves of the widest stride.
 __global__ void __launch_bounds__(256) k_persistent(const Inst* __restrict__ insts,
                                                     const Pack* __restrict__ packs, int npacks,
                                                     int* __restrict__ head) {
-  extern __shared__ __attribute__((aligned(16))) char smem[];
+  __shared__ SegSync sy[kPackWaves];
+  __shared__ __attribute__((aligned(16))) float ringA[kPackWaves][kChunk * kMaxC];
+  __shared__ __attribute__((aligned(16))) float ringB[kPackWaves][kChunk * kMaxC];
   __shared__ int s_item;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  SegSync* sy = reinterpret_cast<SegSync*>(smem);
-  float* ring = reinterpret_cast<float*>(smem + kPackWaves * sizeof(SegSync)) + wv * kRing * kMaxC;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(head, 1);
     reset_sync(sy + wv, lane);
     __syncthreads();
-    const int item = s_item;
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
     if (item >= npacks) break;
     const int ii = packs[item].inst[wv];
     if (ii < 0) {
@@ -128,10 +132,7 @@ __global__ void __launch_bounds__(256) k_persistent(const Inst* __restrict__ ins
       const int seg = packs[item].seg[wv];
       const int first = packs[item].first[wv];
       set_prio(in.prio);
-      if (in.stride == 32)
-        pack_dispatch<32>(in, seg, lane, sy + first, ring);
-      else
-        pack_dispatch<256>(in, seg, lane, sy + first, ring);
+      pack_dispatch(in, seg, lane, sy + first, ringA[wv], ringB[wv]);
       __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();     // every wave is done with this pack's LDS
@@ -169,74 +170,38 @@ __global__ void k_fill(int* p, int n, int v) {
 
 // ---- launchers ---------------------------------------------------------------
 
-size_t lds_bytes_one(int W, int stride) {
-  return (size_t)W * sizeof(SegSync) + (size_t)W * kRing * stride * sizeof(float);
-}
-
-size_t lds_bytes_persistent() {
-  return (size_t)kPackWaves * sizeof(SegSync) + (size_t)kPackWaves * kRing * kMaxC * sizeof(float);
-}
-
 static bool m_in(int M, const int* menu, int n) {
   for (int i = 0; i < n; ++i)
     if (menu[i] == M) return true;
   return false;
 }
 
+static const int kOneMenu[] = {2, 4, 6, 8, 10, 12, 14, 16};
+static const int kLongMenu[] = {16, 24, 32, 40, 48, 56, 60, 64};
+static const int kPackMenuK[] = {2, 4, 6, 8, 12, 16};
+
 bool geometry_supported_one(int W, int M) {
-  static const int small[] = {2, 4, 6, 8, 10, 12, 14, 16};
-  static const int large[] = {8, 12, 16, 20, 24, 28, 30, 32};
-  if (W >= 1 && W <= 4 && m_in(M, small, 8)) return true;
-  if (W >= 1 && W <= 16 && m_in(M, large, 8)) return true;
+  if (W >= 1 && W <= 4 && m_in(M, kOneMenu, 8)) return true;
+  if (W >= 1 && W <= 8 && m_in(M, kLongMenu, 8)) return true;
   return false;
 }
 
 bool geometry_supported_pack(int W, int M) {
-  static const int menu[] = {2, 4, 6, 8, 12, 16};
-  return (W == 1 || W == 2 || W == 4) && m_in(M, menu, 6);
-}
-
-static hipError_t set_lds_limit(const void* fn, size_t bytes) {
-  if (bytes <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return (W == 1 || W == 2 || W == 4) && m_in(M, kPackMenuK, 6);
 }
 
 hipError_t launch_one(const Inst& in, hipStream_t st) {
-  const size_t lds = lds_bytes_one(in.W, in.stride);
-  static const int small[] = {2, 4, 6, 8, 10, 12, 14, 16};
-  const bool use_small = in.W <= 4 && m_in(in.M, small, 8);
   const dim3 block(kWave * in.W);
-  hipError_t e;
-  if (use_small) {
-    if (in.stride == 32) {
-      e = set_lds_limit((const void*)k_one<32>, lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k_one<32>, dim3(1), block, lds, st, in);
-    } else {
-      e = set_lds_limit((const void*)k_one<256>, lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k_one<256>, dim3(1), block, lds, st, in);
-    }
-  } else {
-    if (in.stride == 32) {
-      e = set_lds_limit((const void*)k_one_long<32>, lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k_one_long<32>, dim3(1), block, lds, st, in);
-    } else {
-      e = set_lds_limit((const void*)k_one_long<256>, lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k_one_long<256>, dim3(1), block, lds, st, in);
-    }
-  }
+  if (in.W <= 4 && m_in(in.M, kOneMenu, 8))
+    hipLaunchKernelGGL(k_one, dim3(1), block, 0, st, in);
+  else
+    hipLaunchKernelGGL(k_one_long, dim3(1), block, 0, st, in);
   return hipGetLastError();
 }
 
 hipError_t launch_persistent(const Inst* d_insts, const Pack* d_packs, int npacks, int* d_head,
                              int grid, hipStream_t st) {
-  const size_t lds = lds_bytes_persistent();
-  hipError_t e = set_lds_limit((const void*)k_persistent, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_persistent, dim3(grid), dim3(kWave * kPackWaves), lds, st, d_insts, d_packs,
+  hipLaunchKernelGGL(k_persistent, dim3(grid), dim3(kWave * kPackWaves), 0, st, d_insts, d_packs,
                      npacks, d_head);
   return hipGetLastError();
 }
@@ -264,8 +229,8 @@ hipError_t launch_fill(int* p, int n, int v, hipStream_t st) {
 
 int persistent_blocks_per_cu() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent, kWave * kPackWaves,
-                                                   lds_bytes_persistent()) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent, kWave * kPackWaves, 0) !=
+      hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }

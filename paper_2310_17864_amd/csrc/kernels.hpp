@@ -6,8 +6,6 @@
 
 namespace ctca {
 
-size_t lds_bytes_one(int W, int stride);
-size_t lds_bytes_persistent();
 bool geometry_supported_one(int W, int M);
 bool geometry_supported_pack(int W, int M);
 hipError_t launch_one(const Inst& in, hipStream_t st);

@@ -1,0 +1,220 @@
+// Continuous-batching scheduler for the alignment server: request FIFO,
+// admission against a backpointer-memory budget, a first-fit arena, and
+// completion bookkeeping.  It knows nothing about HIP: an Executor launches a
+// group of admitted requests and later reports them done, so the same logic
+// runs against the GPU executor (server.cpp) and a CPU fake (tests).
+//
+// Admission is strictly FIFO: the oldest waiting request is admitted as soon
+// as (a) fewer than max_inflight requests are on the device, (b) its charge
+// fits the budget next to everything in flight, and (c) its workspace fits a
+// free arena range; nothing behind it may overtake it, so nothing starves.
+// A request whose charge alone exceeds the budget is refused at submit.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <map>
+#include <vector>
+
+namespace ctca {
+
+inline double mono_now() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over offsets [0, size), 256-byte granules, coalescing frees.
+class ArenaMap {
+ public:
+  explicit ArenaMap(size_t size = 0) { reset(size); }
+  void reset(size_t size) {
+    free_.clear();
+    size_ = size / 256 * 256;
+    if (size_) free_[0] = size_;
+  }
+  // returns offset or SIZE_MAX
+  size_t alloc(size_t len) {
+    len = (len + 255) / 256 * 256;
+    if (len == 0) len = 256;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= len) {
+        const size_t off = it->first, rem = it->second - len;
+        free_.erase(it);
+        if (rem) free_[off + len] = rem;
+        used_ += len;
+        return off;
+      }
+    }
+    return SIZE_MAX;
+  }
+  void release(size_t off, size_t len) {
+    len = (len + 255) / 256 * 256;
+    if (len == 0) len = 256;
+    used_ -= len;
+    auto it = free_.emplace(off, len).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+  size_t size() const { return size_; }
+  size_t largest_free() const {
+    size_t m = 0;
+    for (auto& kv : free_) m = std::max(m, kv.second);
+    return m;
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t size_ = 0, used_ = 0;
+};
+
+struct SchedReq {
+  uint64_t ticket = 0;
+  size_t charge = 0;      // bytes counted against the budget
+  size_t ws_bytes = 0;    // bytes taken from the arena
+  size_t arena_off = SIZE_MAX;
+  int status = -1;        // -1 while pending
+  double t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
+  void* user = nullptr;   // executor payload (descriptor of the alignment)
+};
+
+struct SchedStats {
+  uint64_t submitted = 0, completed = 0, launches = 0, timeouts = 0;
+  size_t peak_charge = 0;
+  int peak_inflight = 0;
+  bool budget_violated = false;   // stays false: checked on every admission
+};
+
+template <class Exec>
+class Scheduler {
+ public:
+  Scheduler(Exec* ex, size_t budget, size_t arena_bytes, int max_inflight, double watchdog_s)
+      : ex_(ex), budget_(budget), arena_(arena_bytes), max_inflight_(max_inflight),
+        watchdog_s_(watchdog_s) {}
+
+  // 0 ok, 3 (ENOMEM) if the request can never fit, 5 (EAGAIN) if the queue is full
+  int submit(SchedReq* r, size_t queue_cap) {
+    if (r->charge > budget_ || r->ws_bytes > arena_.size()) return 3;
+    if (fifo_.size() >= queue_cap) return 5;
+    r->t_submit = mono_now();
+    fifo_.push_back(r);
+    stats_.submitted++;
+    return 0;
+  }
+
+  // One scheduling round: admit what fits, launch it, retire finished
+  // launches.  Returns the requests completed in this round.
+  std::vector<SchedReq*> step() {
+    std::vector<SchedReq*> done;
+    retire(done);
+    std::vector<SchedReq*> batch;
+    while (!fifo_.empty() && ex_->can_launch()) {
+      SchedReq* r = fifo_.front();
+      if (inflight_reqs_ >= max_inflight_) break;
+      if (charge_ + r->charge > budget_) break;
+      const size_t off = arena_.alloc(r->ws_bytes);
+      if (off == SIZE_MAX) break;
+      r->arena_off = off;
+      r->t_admit = mono_now();
+      charge_ += r->charge;
+      if (charge_ > budget_) stats_.budget_violated = true;
+      stats_.peak_charge = std::max(stats_.peak_charge, charge_);
+      inflight_reqs_++;
+      stats_.peak_inflight = std::max(stats_.peak_inflight, inflight_reqs_);
+      fifo_.pop_front();
+      batch.push_back(r);
+      if ((int)batch.size() >= ex_->max_batch()) break;
+    }
+    if (!batch.empty()) {
+      const double t = mono_now();
+      for (auto* r : batch) r->t_launch = t;
+      Launch L;
+      L.reqs = batch;
+      L.t_launch = t;
+      L.handle = ex_->launch(batch);
+      launches_.push_back(L);
+      stats_.launches++;
+    }
+    return done;
+  }
+
+  bool idle() const { return fifo_.empty() && launches_.empty(); }
+  size_t waiting() const { return fifo_.size(); }
+  int inflight() const { return inflight_reqs_; }
+  size_t charge_inflight() const { return charge_; }
+  const SchedStats& stats() const { return stats_; }
+  const ArenaMap& arena() const { return arena_; }
+
+ private:
+  struct Launch {
+    std::vector<SchedReq*> reqs;
+    typename Exec::Handle handle;
+    double t_launch = 0;
+    bool timed_out = false;
+  };
+
+  void retire(std::vector<SchedReq*>& done) {
+    for (size_t i = 0; i < launches_.size();) {
+      Launch& L = launches_[i];
+      std::vector<int> st;
+      if (ex_->poll(L.handle, L.reqs, st)) {
+        const double t = mono_now();
+        for (size_t k = 0; k < L.reqs.size(); ++k) {
+          SchedReq* r = L.reqs[k];
+          arena_.release(r->arena_off, r->ws_bytes);
+          charge_ -= r->charge;
+          inflight_reqs_--;
+          if (!L.timed_out) {
+            r->status = st[k];
+            r->t_done = t;
+            done.push_back(r);
+            stats_.completed++;
+          }
+        }
+        ex_->release(L.handle);
+        launches_.erase(launches_.begin() + i);
+        continue;
+      }
+      // watchdog: report a launch that never finishes; its memory stays
+      // reserved until the executor reports it done
+      if (!L.timed_out && watchdog_s_ > 0 && mono_now() - L.t_launch > watchdog_s_) {
+        L.timed_out = true;
+        stats_.timeouts++;
+        const double t = mono_now();
+        for (SchedReq* r : L.reqs) {
+          r->status = 4;   // EDEVICE
+          r->t_done = t;
+          done.push_back(r);
+          stats_.completed++;
+        }
+      }
+      ++i;
+    }
+  }
+
+  Exec* ex_;
+  size_t budget_;
+  ArenaMap arena_;
+  int max_inflight_;
+  double watchdog_s_;
+  std::deque<SchedReq*> fifo_;
+  std::vector<Launch> launches_;
+  size_t charge_ = 0;
+  int inflight_reqs_ = 0;
+  SchedStats stats_;
+};
+
+}  // namespace ctca

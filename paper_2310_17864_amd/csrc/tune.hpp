@@ -17,7 +17,7 @@ struct Geo {
 
 // M values compiled into each kernel family.
 constexpr int kMenuOne[] = {2, 4, 6, 8, 10, 12, 14, 16};          // k_one, W <= 4
-constexpr int kMenuLong[] = {8, 12, 16, 20, 24, 28, 30, 32};      // k_one_long, W <= 16
+constexpr int kMenuLong[] = {16, 24, 32, 40, 48, 56, 60, 64};     // k_one_long, W <= 8
 constexpr int kMenuPack[] = {2, 4, 6, 8, 12, 16};                 // k_persistent, W in {1,2,4}
 
 // Geometry is usable iff it covers S and the top segment holds S-1 and S-2
@@ -60,7 +60,7 @@ struct TuneTable {
     }
     for (int M : kMenuLong) {
       const int W = (S + kWave * M - 1) / (kWave * M);
-      if (W <= 16 && geo_ok(S, W, M)) return Geo{W, M};
+      if (W <= 8 && geo_ok(S, W, M)) return Geo{W, M};
     }
     return Geo{0, 0};
   }

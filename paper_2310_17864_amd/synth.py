@@ -44,7 +44,7 @@ import numpy as np
 __all__ = [
     "Utterance", "Workload", "draw_labels", "planted_states", "emissions_around",
     "utterance", "cfg_single", "cfg_plain_batch", "cfg_long", "cfg_batched",
-    "cfg_serving", "poisson_arrivals", "pack",
+    "cfg_serving", "poisson_arrivals", "pack", "packed_parallel",
 ]
 
 
@@ -188,19 +188,35 @@ def cfg_long(T: int = 90_000, C: int = 32, L: int = 15_000, seed: int = 3) -> Wo
     return Workload(f"long_T{T}_C{C}_L{L}", [u], {"seed": seed})
 
 
+def _spec_batched(r: np.random.Generator, C: int, t_lo: int, t_hi: int):
+    T = _log_uniform_T(r, t_lo, t_hi)
+    L = _L_quarter_sixth(r, T)
+    return T, int(C), L
+
+
+def _spec_serving(r: np.random.Generator, classes, t_lo: int, t_hi: int):
+    T = _log_uniform_T(r, t_lo, t_hi)
+    C = int(classes[int(r.integers(0, len(classes)))])
+    L = _L_quarter_sixth(r, T)
+    return T, C, L
+
+
+def _batched_classes(top: np.random.Generator, n: int, classes):
+    k = len(classes)
+    cs = np.array([classes[i % k] for i in range(n)], dtype=np.int64)
+    return cs[top.permutation(n)]
+
+
 def cfg_batched(n: int = 4096, t_lo: int = 100, t_hi: int = 6000,
                 classes=(32, 256), seed: int = 4) -> Workload:
     """n utterances, T log-uniform [t_lo, t_hi], L ~ U{ceil(T/6)..floor(T/4)},
     exactly n/len(classes) per class count by a seeded permutation, labels i.i.d."""
     rngs, top = _children(seed, n)
-    k = len(classes)
-    cs = np.array([classes[i % k] for i in range(n)], dtype=np.int64)
-    cs = cs[top.permutation(n)]
+    cs = _batched_classes(top, n, classes)
     utts = []
     for r, C in zip(rngs, cs):
-        T = _log_uniform_T(r, t_lo, t_hi)
-        L = _L_quarter_sixth(r, T)
-        utts.append(utterance(r, T, int(C), L, 0, 6.0, 1.0, None))
+        T, C, L = _spec_batched(r, C, t_lo, t_hi)
+        utts.append(utterance(r, T, C, L, 0, 6.0, 1.0, None))
     return Workload(f"batched{n}_T{t_lo}-{t_hi}_C{'/'.join(map(str, classes))}",
                     utts, {"seed": seed})
 
@@ -212,11 +228,72 @@ def cfg_serving(pool: int = 4096, t_lo: int = 100, t_hi: int = 30_000,
     rngs, _ = _children(seed, pool)
     utts = []
     for r in rngs:
-        T = _log_uniform_T(r, t_lo, t_hi)
-        C = int(classes[int(r.integers(0, len(classes)))])
-        L = _L_quarter_sixth(r, T)
+        T, C, L = _spec_serving(r, classes, t_lo, t_hi)
         utts.append(utterance(r, T, C, L, 0, 6.0, 1.0, None))
     return Workload(f"serving_pool{pool}_T{t_lo}-{t_hi}", utts, {"seed": seed})
+
+
+# ---- the same workloads generated by a pool of forked workers -------------
+
+_PAR = {}
+
+
+def _par_work(i: int):
+    """Worker: regenerate utterance i from its own stream into the shared
+    emission buffer; return its labels."""
+    g = _PAR
+    r = np.random.default_rng(g["seqs"][i])
+    if g["kind"] == "batched":
+        T, C, L = _spec_batched(r, g["cs"][i], g["t_lo"], g["t_hi"])
+    else:
+        T, C, L = _spec_serving(r, g["classes"], g["t_lo"], g["t_hi"])
+    u = utterance(r, T, C, L, 0, 6.0, 1.0, None)
+    off = g["em_off"][i]
+    g["em"][off:off + T * C] = u.emission.reshape(-1)
+    return i, u.labels
+
+
+def packed_parallel(kind: str, n: int, workers: int = 8, t_lo: int = 100, t_hi: int = 6000,
+                    classes=(32, 256), seed: int = 4):
+    """pack(cfg_batched(...).utts) (kind="batched") or pack(cfg_serving(...).utts)
+    (kind="serving"), bit-identical, generated by `workers` forked processes
+    writing into one anonymous shared mapping.  Call before any GPU work."""
+    import mmap
+    import multiprocessing as mp
+    seqs = np.random.SeedSequence(seed).spawn(n + 1)
+    top = np.random.default_rng(seqs[n])
+    T = np.zeros(n, np.int32)
+    C = np.zeros(n, np.int32)
+    L = np.zeros(n, np.int32)
+    cs = _batched_classes(top, n, classes) if kind == "batched" else None
+    for i in range(n):       # shapes only: the first draws of each stream
+        r = np.random.default_rng(seqs[i])
+        if kind == "batched":
+            T[i], C[i], L[i] = _spec_batched(r, cs[i], t_lo, t_hi)
+        else:
+            T[i], C[i], L[i] = _spec_serving(r, classes, t_lo, t_hi)
+    em_off = np.zeros(n, np.int64)
+    lab_off = np.zeros(n, np.int64)
+    fr_off = np.zeros(n, np.int64)
+    e = l = f = 0
+    for i in range(n):
+        em_off[i], lab_off[i], fr_off[i] = e, l, f
+        e += (int(T[i]) * int(C[i]) + 63) // 64 * 64
+        l += int(L[i])
+        f += int(T[i])
+    buf = mmap.mmap(-1, max(e, 1) * 4)
+    em = np.frombuffer(buf, dtype=np.float32)
+    _PAR.clear()
+    _PAR.update(kind=kind, seqs=seqs, cs=cs, classes=classes, t_lo=t_lo, t_hi=t_hi,
+                em_off=em_off, em=em)
+    lab = np.zeros(max(l, 1), np.int32)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(max(1, workers)) as pool:
+        for i, y in pool.imap_unordered(_par_work, range(n), chunksize=4):
+            lab[lab_off[i]:lab_off[i] + len(y)] = y
+    _PAR.clear()
+    return dict(em=em, lab=lab, em_off=em_off, lab_off=lab_off, fr_off=fr_off,
+                T=T, C=C, L=L, frames=f, _buf=buf)
 
 
 def poisson_arrivals(rate: float, seconds: float, pool: int, seed: int = 5):

@@ -1,0 +1,206 @@
+// CPU test of the server's scheduling core with a fake executor: budget
+// invariant, strict FIFO admission, refusal of oversize requests, the
+// watchdog, and the arena allocator.  Built with g++ (optionally under
+// AddressSanitizer/UBSan) by tests/test_sched_native.py.
+#include <cassert>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <set>
+#include <thread>
+#include <vector>
+
+#include "../../paper_2310_17864_amd/csrc/sched.hpp"
+
+using namespace ctca;
+
+static int failures = 0;
+#define CHECK(c)                                                        \
+  do {                                                                  \
+    if (!(c)) {                                                         \
+      std::fprintf(stderr, "CHECK failed %s:%d: %s\n", __FILE__, __LINE__, #c); \
+      ++failures;                                                       \
+    }                                                                   \
+  } while (0)
+
+// Completes each launch after `lag` polls; a launch containing a request
+// with `stuck` set never completes.  Tracks the charge on the "device".
+struct FakeExec {
+  struct Handle {
+    int polls = 0;
+    bool stuck = false;
+  };
+  int lag = 3;
+  int cap = 64;
+  int launches_open = 0;
+  size_t device_charge = 0, peak = 0, budget = 0;
+  bool violated = false;
+  std::vector<uint64_t> admit_order;
+  bool can_launch() const { return launches_open < 8; }
+  int max_batch() const { return cap; }
+  Handle launch(std::vector<SchedReq*>& reqs) {
+    Handle h;
+    for (auto* r : reqs) {
+      admit_order.push_back(r->ticket);
+      device_charge += r->charge;
+      if (r->user) h.stuck = true;
+    }
+    peak = std::max(peak, device_charge);
+    if (device_charge > budget) violated = true;
+    ++launches_open;
+    return h;
+  }
+  bool poll(Handle& h, const std::vector<SchedReq*>& reqs, std::vector<int>& st) {
+    if (h.stuck || ++h.polls < lag) return false;
+    st.assign(reqs.size(), 0);
+    for (auto* r : reqs) device_charge -= r->charge;
+    return true;
+  }
+  void release(Handle&) { --launches_open; }
+};
+
+static void test_budget_fifo() {
+  std::mt19937_64 rng(7);
+  const size_t budget = 1000;
+  FakeExec ex;
+  ex.budget = budget;
+  Scheduler<FakeExec> s(&ex, budget, 4096, 1 << 20, 0.0);
+  std::vector<SchedReq> reqs(2000);
+  size_t next = 0, done = 0;
+  uint64_t t = 1;
+  while (done < reqs.size()) {
+    // a random number of arrivals per round
+    const int arrivals = (int)(rng() % 4);
+    for (int a = 0; a < arrivals && next < reqs.size(); ++a) {
+      SchedReq& r = reqs[next++];
+      r.ticket = t++;
+      r.charge = 1 + rng() % 400;
+      r.ws_bytes = 256 * (1 + rng() % 3);
+      CHECK(s.submit(&r, 1 << 20) == 0);
+    }
+    auto fin = s.step();
+    done += fin.size();
+    CHECK(s.charge_inflight() <= budget);
+  }
+  CHECK(!ex.violated);
+  CHECK(ex.peak <= budget);
+  CHECK(!s.stats().budget_violated);
+  // strict FIFO: admitted in submission order
+  for (size_t i = 1; i < ex.admit_order.size(); ++i) CHECK(ex.admit_order[i] > ex.admit_order[i - 1]);
+  CHECK(ex.admit_order.size() == reqs.size());
+  CHECK(s.idle());
+  CHECK(s.arena().used() == 0);
+}
+
+static void test_refusals() {
+  FakeExec ex;
+  ex.budget = 100;
+  Scheduler<FakeExec> s(&ex, 100, 1024, 10, 0.0);
+  SchedReq big;
+  big.charge = 101;
+  big.ws_bytes = 256;
+  CHECK(s.submit(&big, 16) == 3);            // ENOMEM: can never fit
+  SchedReq huge_ws;
+  huge_ws.charge = 10;
+  huge_ws.ws_bytes = 4096;
+  CHECK(s.submit(&huge_ws, 16) == 3);        // larger than the arena
+  std::vector<SchedReq> q(3);
+  for (auto& r : q) {
+    r.charge = 1;
+    r.ws_bytes = 256;
+  }
+  CHECK(s.submit(&q[0], 2) == 0);
+  CHECK(s.submit(&q[1], 2) == 0);
+  CHECK(s.submit(&q[2], 2) == 5);            // EAGAIN: queue full
+}
+
+static void test_max_inflight_and_no_overtake() {
+  FakeExec ex;
+  ex.budget = 100;
+  ex.lag = 2;
+  Scheduler<FakeExec> s(&ex, 100, 1 << 16, 2, 0.0);
+  std::vector<SchedReq> r(5);
+  for (int i = 0; i < 5; ++i) {
+    r[i].ticket = i + 1;
+    r[i].charge = (i == 1) ? 96 : 5;   // the second one blocks on the budget
+    r[i].ws_bytes = 256;
+    CHECK(s.submit(&r[i], 16) == 0);
+  }
+  s.step();
+  // only the first is admitted: #2 does not fit next to it and nobody overtakes #2
+  CHECK(s.inflight() == 1);
+  CHECK(s.waiting() == 4);
+  int guard = 0;
+  while (!s.idle() && guard++ < 100) {
+    s.step();
+    CHECK(s.inflight() <= 2);
+  }
+  CHECK(s.idle());
+  for (size_t i = 1; i < ex.admit_order.size(); ++i) CHECK(ex.admit_order[i] > ex.admit_order[i - 1]);
+}
+
+static void test_watchdog() {
+  FakeExec ex;
+  ex.budget = 100;
+  ex.cap = 1;                       // one request per launch
+  Scheduler<FakeExec> s(&ex, 100, 1 << 16, 10, 0.05);
+  std::vector<SchedReq> r(3);
+  int tag = 1;
+  for (int i = 0; i < 3; ++i) {
+    r[i].ticket = i + 1;
+    r[i].charge = 10;
+    r[i].ws_bytes = 256;
+    r[i].user = (i == 1) ? &tag : nullptr;   // request 2 hangs
+    CHECK(s.submit(&r[i], 16) == 0);
+  }
+  std::vector<SchedReq*> fin;
+  const double t0 = mono_now();
+  while (fin.size() < 3 && mono_now() - t0 < 2.0) {
+    auto f = s.step();
+    fin.insert(fin.end(), f.begin(), f.end());
+    std::this_thread::sleep_for(std::chrono::milliseconds(1));
+  }
+  CHECK(fin.size() == 3);
+  CHECK(r[0].status == 0 && r[2].status == 0);
+  CHECK(r[1].status == 4);                  // EDEVICE from the watchdog
+  CHECK(s.stats().timeouts == 1);
+  CHECK(s.charge_inflight() == 10);         // the hung launch keeps its memory
+}
+
+static void test_arena() {
+  std::mt19937_64 rng(3);
+  ArenaMap a(1 << 20);
+  std::vector<std::pair<size_t, size_t>> live;
+  for (int it = 0; it < 20000; ++it) {
+    if (live.empty() || rng() % 2) {
+      const size_t len = 256 * (1 + rng() % 64);
+      const size_t off = a.alloc(len);
+      if (off != SIZE_MAX) {
+        for (auto& l : live) CHECK(off + len <= l.first || l.first + l.second <= off);
+        CHECK(off + len <= a.size());
+        live.push_back({off, len});
+      }
+    } else {
+      const size_t k = rng() % live.size();
+      a.release(live[k].first, live[k].second);
+      live.erase(live.begin() + k);
+    }
+  }
+  for (auto& l : live) a.release(l.first, l.second);
+  CHECK(a.used() == 0);
+  CHECK(a.largest_free() == a.size());      // fully coalesced again
+}
+
+int main() {
+  test_budget_fifo();
+  test_refusals();
+  test_max_inflight_and_no_overtake();
+  test_watchdog();
+  test_arena();
+  if (failures) {
+    std::fprintf(stderr, "%d check(s) failed\n", failures);
+    return 1;
+  }
+  std::printf("sched ok\n");
+  return 0;
+}

@@ -1,0 +1,119 @@
+"""The continuous-batching server on the GPU: every request's result is
+bit-identical to the CPU oracle whether it runs alone or mixed with others,
+under a large and a tiny backpointer budget, and oversize requests are
+refused."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import same_bits, torch_dev
+from paper_2310_17864_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _pool():
+    wl = synth.cfg_serving(pool=40, t_hi=14000, seed=21)
+    utts = list(wl.utts)
+    rng = np.random.default_rng(9)
+    utts.append(synth.utterance(rng, 300, 17, 40, 0, 6.0, 1.0, None))      # padded class count
+    utts.append(synth.utterance(rng, 500, 100, 90, 3, 6.0, 1.0, None))     # padded, blank 3
+    bad = synth.utterance(rng, 200, 32, 30, 0, 6.0, 1.0, None)
+    bad.labels[5] = 0                                                      # label == blank
+    utts.append(bad)
+    utts.append(synth.Utterance(np.zeros((3, 32), np.float32), np.array([4, 4], np.int32), 0))
+    return utts
+
+
+def _upload(utts):
+    torch, dev = torch_dev()
+    out = []
+    for u in utts:
+        out.append(dict(em=torch.from_numpy(u.emission).to(dev),
+                        lab=torch.from_numpy(u.labels).to(dev) if u.L else
+                        torch.empty(0, dtype=torch.int32, device=dev),
+                        path=torch.full((u.T,), -7, dtype=torch.int32, device=dev),
+                        sc=torch.empty(u.T, dtype=torch.float32, device=dev),
+                        tot=torch.empty(1, dtype=torch.float32, device=dev)))
+    torch.cuda.synchronize()
+    return out
+
+
+def _check(utts, bufs, results):
+    errs = []
+    for i, (u, b, (st, tm)) in enumerate(zip(utts, bufs, results)):
+        st_o, p_o, s_o, t_o = oracle.align_f32(u.emission, u.labels, u.blank)
+        if st != st_o:
+            errs.append(f"req {i}: status {st} vs oracle {st_o}")
+            continue
+        if not same_bits(b["path"].cpu().numpy(), p_o) or not same_bits(b["sc"].cpu().numpy(), s_o):
+            errs.append(f"req {i}: path/scores differ (T={u.T} L={u.L} C={u.C})")
+        if st_o in (0, 2) and np.float32(b["tot"].cpu().numpy()[0]).view(np.uint32) != \
+                np.float32(t_o).view(np.uint32):
+            errs.append(f"req {i}: total differs")
+        if not (tm[0] <= tm[1] <= tm[2] <= tm[3]):
+            errs.append(f"req {i}: timestamps out of order {tm}")
+    return errs
+
+
+def _serve(utts, bufs, budget, stagger=False):
+    import paper_2310_17864_amd as ca
+    srv = ca.Server(budget)
+    tickets = []
+    for i, (u, b) in enumerate(zip(utts, bufs)):
+        tickets.append(srv.submit(b["em"], b["lab"], b["path"], b["sc"], b["tot"], u.blank))
+        if stagger and i % 5 == 4:
+            time.sleep(0.002)     # later arrivals join while earlier ones run
+    res = [srv.wait(t) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    return res, stats
+
+
+def test_server_mixed_matches_oracle():
+    utts = _pool()
+    bufs = _upload(utts)
+    res, stats = _serve(utts, bufs, 64 << 30, stagger=True)
+    assert _check(utts, bufs, res) == []
+    assert stats["budget_violated"] == 0 and stats["completed"] == len(utts)
+
+
+def test_server_tiny_budget_serialises_but_matches():
+    utts = _pool()
+    bufs = _upload(utts)
+    charges = [u.T * (2 * u.L + 1) // 4 + 1 for u in utts]
+    budget = int(2.2 * max(charges))           # at most ~2 big requests at once
+    res, stats = _serve(utts, bufs, budget)
+    assert _check(utts, bufs, res) == []
+    assert stats["peak_charge_bytes"] <= budget
+    assert stats["budget_violated"] == 0
+
+
+def test_server_alone_equals_mixed():
+    import paper_2310_17864_amd as ca
+    utts = _pool()[:12]
+    bufs = _upload(utts)
+    _serve(utts, bufs, 64 << 30)
+    mixed = [(b["path"].cpu().numpy().copy(), b["sc"].cpu().numpy().copy()) for b in bufs]
+    srv = ca.Server(64 << 30)
+    for u, b, (p, s) in zip(utts, bufs, mixed):
+        b["path"].fill_(-7)
+        t = srv.submit(b["em"], b["lab"], b["path"], b["sc"], b["tot"], u.blank)
+        srv.wait(t)
+        assert np.array_equal(b["path"].cpu().numpy(), p)
+        assert np.array_equal(b["sc"].cpu().numpy().view(np.uint32), s.view(np.uint32))
+    srv.close()
+
+
+def test_server_refuses_oversize():
+    import paper_2310_17864_amd as ca
+    torch, dev = torch_dev()
+    u = synth.utterance(np.random.default_rng(1), 4000, 32, 800, 0, 6.0, 1.0, None)
+    b = _upload([u])[0]
+    srv = ca.Server(1 << 16)
+    with pytest.raises(ca.CtcAlignError) as ei:
+        srv.submit(b["em"], b["lab"], b["path"], b["sc"], b["tot"])
+    assert ei.value.code == ca.ENOMEM
+    srv.close()
