@@ -157,6 +157,20 @@ def run_batched(args):
     exact = bool(np.array_equal(st, ref[0]) and np.array_equal(paths, ref[1])
                  and np.array_equal(scores.view(np.uint32), ref[2].view(np.uint32))
                  and np.array_equal(totals[ok].view(np.uint32), ref[3][ok].view(np.uint32)))
+    mismatch = None
+    if not exact:
+        bad = []
+        for i in range(plan.n):
+            a, b = int(pk["fr_off"][i]), int(pk["fr_off"][i]) + int(pk["T"][i])
+            if (st[i] != ref[0][i] or not np.array_equal(paths[a:b], ref[1][a:b])
+                    or not np.array_equal(scores[a:b].view(np.uint32), ref[2][a:b].view(np.uint32))
+                    or (ref[0][i] == 0 and totals[i].view(np.uint32) != ref[3][i].view(np.uint32))):
+                nd = int(np.sum(paths[a:b] != ref[1][a:b]))
+                bad.append({"i": i, "T": int(pk["T"][i]), "L": int(pk["L"][i]), "C": int(pk["C"][i]),
+                            "status": int(st[i]), "ref_status": int(ref[0][i]), "path_diff": nd,
+                            "first_diff": int(np.argmax(paths[a:b] != ref[1][a:b])) if nd else -1})
+        mismatch = {"utterances": len(bad), "first": bad[:8]}
+        log("MISMATCH", json.dumps(mismatch))
     bytes_alg = algorithmic_bytes(pk["T"], pk["C"], pk["L"])
     ops_alg = algorithmic_ops(pk["T"], pk["L"])
     hbm = bytes_alg / (ms / 1e3) / 1e9
@@ -185,6 +199,7 @@ def run_batched(args):
                    "utterances": args.n, "frames": F, "state_steps": int(np.sum(
                        pk["T"].astype(np.int64) * (2 * pk["L"].astype(np.int64) + 1)))},
         "bit_exact": exact,
+        "mismatch": mismatch,
         "wall_s_timed": wall,
         "ms_min": float(np.min(per)), "ms_max": float(np.max(per)),
         "plain_per_utterance": plain,
@@ -254,21 +269,176 @@ def run_single(args, long_form: bool):
     }
 
 
+def run_serving(args, pk=None):
+    """Open-loop serving: Poisson arrivals drawn from a device-resident pool,
+    p50/p99 latency from scheduled arrival to observed completion; then the
+    saturated throughput (whole pool submitted at once) and the plain
+    per-utterance loop on the same request mix."""
+    import ctypes
+
+    import oracle
+    from paper_2310_17864_amd import synth
+    t = time.time()
+    if pk is None:
+        pk = synth.packed_parallel("serving", args.pool, workers=cpu_threads(), t_lo=100,
+                                   t_hi=30000, seed=5)
+    log(f"serving pool: {args.pool} utterances, {pk['frames']} frames in {time.time() - t:.1f}s")
+    times, idx = synth.poisson_arrivals(args.rate, args.serve_seconds, args.pool, seed=5)
+
+    import torch
+
+    import paper_2310_17864_amd as ca
+    from paper_2310_17864_amd import _lib
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    em = torch.from_numpy(pk["em"]).to(dev)
+    lab = torch.from_numpy(pk["lab"]).to(dev)
+    Tn = pk["T"].astype(np.int64)
+    fr_req = np.concatenate([[0], np.cumsum(Tn[idx])])
+    paths = torch.empty(max(int(fr_req[-1]), 1), dtype=torch.int32, device=dev)
+    scores = torch.empty(max(int(fr_req[-1]), 1), dtype=torch.float32, device=dev)
+    totals = torch.empty(max(len(idx), 1), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    emp, labp, pp, sp, tp = em.data_ptr(), lab.data_ptr(), paths.data_ptr(), scores.data_ptr(), totals.data_ptr()
+
+    def request(k, i, f0):
+        return _lib.Request(emp + 4 * int(pk["em_off"][i]), int(pk["T"][i]), int(pk["C"][i]),
+                            labp + 4 * int(pk["lab_off"][i]), int(pk["L"][i]), 0,
+                            pp + 4 * int(f0), sp + 4 * int(f0), tp + 4 * k)
+
+    srv = ca.Server(args.budget_gb << 30)
+    tk = ctypes.c_uint64()
+    tickets = []
+    t0 = time.monotonic() + 0.05
+    last_log = time.monotonic()
+    for k, (a, i) in enumerate(zip(times, idx)):
+        now = time.monotonic()
+        if t0 + a > now:
+            time.sleep(t0 + a - now)
+        rc = lib.ctcalign_server_submit(srv.handle, ctypes.byref(request(k, i, fr_req[k])), ctypes.byref(tk))
+        _lib.check(rc, "submit")
+        tickets.append(tk.value)
+        if time.monotonic() - last_log > 10:
+            log(f"serving: {k} requests submitted")
+            last_log = time.monotonic()
+    st = ctypes.c_int32()
+    tm = _lib.Timing()
+    lat, done, statuses = [], [], []
+    for k, tkt in enumerate(tickets):
+        _lib.check(lib.ctcalign_server_wait(srv.handle, ctypes.c_uint64(tkt), ctypes.byref(st),
+                                            ctypes.byref(tm)), "wait")
+        lat.append(tm.done_s - (t0 + times[k]))
+        done.append(tm.done_s)
+        statuses.append(st.value)
+    stats = srv.stats()
+    warm = times >= min(args.serve_warmup, args.serve_seconds / 4)
+    lat = np.asarray(lat)
+    served_frames = int(np.sum(Tn[idx]))
+    span = max(done) - (t0 + times[0])
+    # bit-exact check of a sample of served results against the oracle
+    rng = np.random.default_rng(0)
+    sample = rng.choice(len(idx), size=min(args.serve_check, len(idx)), replace=False)
+    exact = True
+    p_host = paths.cpu().numpy()
+    s_host = scores.cpu().numpy()
+    for k in sample:
+        i = idx[k]
+        T, C, L = int(pk["T"][i]), int(pk["C"][i]), int(pk["L"][i])
+        e0 = int(pk["em_off"][i])
+        E = pk["em"][e0:e0 + T * C].reshape(T, C)
+        y = pk["lab"][int(pk["lab_off"][i]):int(pk["lab_off"][i]) + L]
+        st_o, p_o, s_o, _ = oracle.align_f32(E, y, 0)
+        a, b = fr_req[k], fr_req[k] + T
+        exact &= (statuses[k] == st_o and np.array_equal(p_host[a:b], p_o)
+                  and np.array_equal(s_host[a:b].view(np.uint32), s_o.view(np.uint32)))
+    open_loop = {
+        "rate_req_per_s": args.rate, "seconds": args.serve_seconds, "requests": len(idx),
+        "p50_ms": float(np.percentile(lat[warm], 50) * 1e3),
+        "p99_ms": float(np.percentile(lat[warm], 99) * 1e3),
+        "max_ms": float(lat.max() * 1e3),
+        "frames_per_s": served_frames / span,
+        "bit_exact_sample": bool(exact), "sample": int(len(sample)),
+        "peak_inflight": stats["peak_inflight"], "peak_charge_bytes": stats["peak_charge_bytes"],
+        "budget_bytes": stats["budget_bytes"], "budget_violated": bool(stats["budget_violated"]),
+        "launches": stats["launches"],
+    }
+    # saturation: the whole pool at once
+    tickets = []
+    fr_pool = np.concatenate([[0], np.cumsum(Tn)])
+    need = int(fr_pool[-1])
+    if need > paths.numel():
+        paths = torch.empty(need, dtype=torch.int32, device=dev)
+        scores = torch.empty(need, dtype=torch.float32, device=dev)
+        pp, sp = paths.data_ptr(), scores.data_ptr()
+    if args.pool > totals.numel():
+        totals = torch.empty(args.pool, dtype=torch.float32, device=dev)
+        tp = totals.data_ptr()
+    torch.cuda.synchronize()
+    ts = time.monotonic()
+    for i in range(args.pool):
+        _lib.check(lib.ctcalign_server_submit(srv.handle, ctypes.byref(request(i, i, fr_pool[i])),
+                                              ctypes.byref(tk)), "submit")
+        tickets.append(tk.value)
+    last = 0.0
+    for tkt in tickets:
+        lib.ctcalign_server_wait(srv.handle, ctypes.c_uint64(tkt), ctypes.byref(st), ctypes.byref(tm))
+        last = max(last, tm.done_s)
+    sat = float(np.sum(Tn)) / (last - ts)
+    srv.close()
+    # plain per-utterance launches over a sample of the same mix
+    sample = rng.choice(args.pool, size=min(64, args.pool), replace=False)
+    outs = []
+    for i in sample:
+        T, C, L = int(pk["T"][i]), int(pk["C"][i]), int(pk["L"][i])
+        e0 = int(pk["em_off"][i])
+        outs.append((em[e0:e0 + T * C].view(T, C), lab[int(pk["lab_off"][i]):int(pk["lab_off"][i]) + L]))
+    torch.cuda.synchronize()
+    tp0 = time.monotonic()
+    for e, l in outs:
+        ca.align(e, l, 0, sync=False)
+    torch.cuda.synchronize()
+    plain = float(np.sum(Tn[sample])) / (time.monotonic() - tp0)
+    return {"open_loop": open_loop, "saturated_frames_per_s": sat,
+            "plain_per_utterance_frames_per_s": plain, "served_vs_plain": sat / plain,
+            "pool": args.pool, "workload": f"Poisson {args.rate}/s for {args.serve_seconds}s, "
+            f"pool of {args.pool} utterances, T log-uniform 100-30000, C=32/256, "
+            f"budget {args.budget_gb} GB"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batched", choices=["batched", "long", "single"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "long", "single", "serve"])
     ap.add_argument("--n", type=int, default=4096, help="utterances in the batched workload")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="open-loop serving run after the batched bench (0: skip)")
+    ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--pool", type=int, default=1024)
+    ap.add_argument("--budget-gb", type=int, default=64)
+    ap.add_argument("--serve-warmup", type=float, default=5.0)
+    ap.add_argument("--serve-check", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
               f"got --gpus {args.gpus}", file=sys.stderr)
         sys.exit(2)
+    pk_serve = None
+    if args.workload == "serve" or (args.workload == "batched" and args.serve_seconds > 0):
+        # generated before any GPU work: the generator forks worker processes
+        from paper_2310_17864_amd import synth
+        t = time.time()
+        pk_serve = synth.packed_parallel("serving", args.pool, workers=cpu_threads(), t_lo=100,
+                                         t_hi=30000, seed=5)
+        log(f"serving pool generated in {time.time() - t:.1f}s")
     if args.workload == "batched":
         out = run_batched(args)
+        if args.serve_seconds > 0:
+            out["serving"] = run_serving(args, pk_serve)
+    elif args.workload == "serve":
+        out = {"metric": METRIC, "serving": run_serving(args, pk_serve)}
     else:
         out = run_single(args, args.workload == "long")
     print(json.dumps(out), flush=True)

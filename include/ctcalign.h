@@ -93,6 +93,29 @@ int ctcalign_ctx_destroy(ctcalign_ctx *ctx);
  * tuning table: query again after ctcalign_tune. */
 size_t ctcalign_workspace_bytes(ctcalign_ctx *ctx, int32_t T, int32_t L, int32_t C);
 
+/* ---- geometry tuning ------------------------------------------------------
+ * An alignment of S = 2L+1 states runs on W wavefronts with M states per lane
+ * (W*64*M >= S).  kind 0 = single launches, kind 1 = the batched persistent
+ * kernel.  The context's table maps (64-state bucket of S, class of C: C <= 32
+ * or larger) to (W, M); empty buckets use the built-in cost model.  The
+ * autotuner (paper_2310_17864_amd/tune.py) times candidates and fills it. */
+
+/* Sets (W, M) for every S in [s_lo, s_hi] of C's class; W = 0 clears the
+ * range.  EINVAL if the kernels do not compile that geometry or it cannot
+ * hold some S of the range. */
+int ctcalign_tune_set(ctcalign_ctx *ctx, int32_t kind, int32_t s_lo, int32_t s_hi, int32_t C,
+                      int32_t W, int32_t M);
+
+/* The geometry the context picks for (S, C). */
+int ctcalign_tune_get(ctcalign_ctx *ctx, int32_t kind, int32_t S, int32_t C, int32_t *W,
+                      int32_t *M);
+
+/* Writes / reads the table as text lines "kind class bucket W M" (host file
+ * path).  ctcalign_ctx_create loads $CTCALIGN_TUNE_CACHE when it is set.
+ * Entries the kernels cannot run are skipped (EINVAL is returned). */
+int ctcalign_tune_save(ctcalign_ctx *ctx, const char *path);
+int ctcalign_tune_load(ctcalign_ctx *ctx, const char *path);
+
 /* ---- one utterance ------------------------------------------------------ */
 
 /* Aligns one utterance on the default context (created on first use on the

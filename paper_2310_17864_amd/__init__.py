@@ -63,6 +63,25 @@ class Context:
     def workspace_bytes(self, T: int, L: int, C: int) -> int:
         return int(_lib.load().ctcalign_workspace_bytes(self.handle, T, L, C))
 
+    # geometry table (kind 0: single launches, 1: batched persistent kernel)
+    def tune_set(self, kind: int, s_lo: int, s_hi: int, C: int, W: int, M: int):
+        _lib.check(_lib.load().ctcalign_tune_set(self.handle, kind, s_lo, s_hi, C, W, M), "tune_set")
+
+    def tune_clear(self, kind: int, s_lo: int, s_hi: int, C: int):
+        self.tune_set(kind, s_lo, s_hi, C, 0, 0)
+
+    def tune_get(self, kind: int, S: int, C: int):
+        W, M = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(_lib.load().ctcalign_tune_get(self.handle, kind, S, C, ctypes.byref(W),
+                                                 ctypes.byref(M)), "tune_get")
+        return int(W.value), int(M.value)
+
+    def tune_save(self, path: str):
+        _lib.check(_lib.load().ctcalign_tune_save(self.handle, path.encode()), "tune_save")
+
+    def tune_load(self, path: str):
+        _lib.check(_lib.load().ctcalign_tune_load(self.handle, path.encode()), "tune_load")
+
 
 def context(device: Optional[int] = None) -> Context:
     torch = _torch()

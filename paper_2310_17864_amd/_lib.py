@@ -50,6 +50,10 @@ _PROTOS = {
     "ctcalign_plan_run": (ctypes.c_int, [P, P]),
     "ctcalign_plan_destroy": (ctypes.c_int, [P]),
     "ctcalign_align_batched": (ctypes.c_int, [P, I32, P, P, P, P, P, P, P, I32, P, P, P, P, P, P]),
+    "ctcalign_tune_set": (ctypes.c_int, [P, I32, I32, I32, I32, I32, I32]),
+    "ctcalign_tune_get": (ctypes.c_int, [P, I32, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+    "ctcalign_tune_save": (ctypes.c_int, [P, ctypes.c_char_p]),
+    "ctcalign_tune_load": (ctypes.c_int, [P, ctypes.c_char_p]),
     "ctcalign_server_create": (ctypes.c_int, [P, SZ, I32, ctypes.POINTER(P)]),
     "ctcalign_server_submit": (ctypes.c_int, [P, ctypes.POINTER(Request),
                                               ctypes.POINTER(ctypes.c_uint64)]),

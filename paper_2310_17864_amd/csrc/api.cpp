@@ -61,7 +61,7 @@ int launch_single(ctcalign_ctx* ctx, const float* emission, int32_t T, int32_t C
   in.stride = row_stride_for(C);
   in.prio = 0;
   geometry_one(ctx, in);
-  if (!geometry_supported_one(in.W, in.M)) return CTCALIGN_EINVAL;
+  if (!geometry_supported_one(in.W, in.M) || !geo_ok(2 * L + 1, in.W, in.M)) return CTCALIGN_EINVAL;
 
   const size_t need = round_up((size_t)bp_words(T, in.W, in.M) * 4, 256);
   if (workspace) {
@@ -116,6 +116,76 @@ const char* ctcalign_strerror(int status) {
 
 int ctcalign_version(void) { return 100; }
 
+int ctcalign_tune_set(ctcalign_ctx* ctx, int32_t kind, int32_t s_lo, int32_t s_hi, int32_t C,
+                      int32_t W, int32_t M) {
+  if (!ctx || (kind != 0 && kind != 1) || s_lo < 1 || s_hi < s_lo || s_hi > kMaxS || C < 1 ||
+      C > kMaxC)
+    return CTCALIGN_EINVAL;
+  if (W == 0) {
+    ctx->tune.set_range(kind, s_lo, s_hi, C, Geo{0, 0});
+    return CTCALIGN_OK;
+  }
+  const bool ok = kind == 0 ? geometry_supported_one(W, M) : geometry_supported_pack(W, M);
+  if (!ok) return CTCALIGN_EINVAL;
+  // the geometry must hold every S of the range (overrides are per 64-state bucket)
+  const int lo = s_lo / kWave * kWave, hi = std::min<int64_t>(s_hi / kWave * kWave + kWave - 1, kMaxS);
+  for (int S = std::max(lo, 1); S <= hi; ++S)
+    if (S >= s_lo && S <= s_hi && !geo_ok(S, W, M)) return CTCALIGN_EINVAL;
+  ctx->tune.set_range(kind, s_lo, s_hi, C, Geo{W, M});
+  return CTCALIGN_OK;
+}
+
+int ctcalign_tune_get(ctcalign_ctx* ctx, int32_t kind, int32_t S, int32_t C, int32_t* W,
+                      int32_t* M) {
+  if (!ctx || !W || !M || S < 1 || S > kMaxS || C < 1 || C > kMaxC || (kind != 0 && kind != 1))
+    return CTCALIGN_EINVAL;
+  const Geo g = kind == 0 ? ctx->tune.pick_one(S, C) : ctx->tune.pick_pack(S, C, 0);
+  *W = g.W;
+  *M = g.M;
+  return g.W > 0 ? CTCALIGN_OK : CTCALIGN_EINVAL;
+}
+
+int ctcalign_tune_save(ctcalign_ctx* ctx, const char* path) {
+  if (!ctx || !path) return CTCALIGN_EINVAL;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return CTCALIGN_EINVAL;
+  std::fprintf(f, "# libctcalign tuning table v1: kind class bucket W M\n");
+  for (int kind = 0; kind < 2; ++kind)
+    for (int c = 0; c < 2; ++c) {
+      const auto& t = kind == 0 ? ctx->tune.one_override[c] : ctx->tune.pack_override[c];
+      for (size_t b = 0; b < t.size(); ++b)
+        if (t[b].W > 0) std::fprintf(f, "%d %d %zu %d %d\n", kind, c, b, t[b].W, t[b].M);
+    }
+  std::fclose(f);
+  return CTCALIGN_OK;
+}
+
+int ctcalign_tune_load(ctcalign_ctx* ctx, const char* path) {
+  if (!ctx || !path) return CTCALIGN_EINVAL;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return CTCALIGN_EINVAL;
+  char line[256];
+  int rc = CTCALIGN_OK;
+  while (std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#') continue;
+    int kind, c, b, W, M;
+    if (std::sscanf(line, "%d %d %d %d %d", &kind, &c, &b, &W, &M) != 5) continue;
+    if ((kind != 0 && kind != 1) || (c != 0 && c != 1) || b < 0 || b > kMaxS / kWave) {
+      rc = CTCALIGN_EINVAL;
+      continue;
+    }
+    const bool ok = kind == 0 ? geometry_supported_one(W, M) : geometry_supported_pack(W, M);
+    if (!ok) {
+      rc = CTCALIGN_EINVAL;
+      continue;
+    }
+    // applied only where it holds the whole bucket; pick_* re-checks per S
+    ctx->tune.set_range(kind, b * kWave, b * kWave + kWave - 1, c == 0 ? 32 : 256, Geo{W, M});
+  }
+  std::fclose(f);
+  return rc;
+}
+
 int ctcalign_ctx_create(int device, ctcalign_ctx** out) {
   if (!out) return CTCALIGN_EINVAL;
   *out = nullptr;
@@ -136,6 +206,9 @@ int ctcalign_ctx_create(int device, ctcalign_ctx** out) {
   }
   c->num_cu = prop.multiProcessorCount;
   c->tune.load_default(c->num_cu);
+  if (const char* tc = std::getenv("CTCALIGN_TUNE_CACHE")) {
+    if (ctcalign_tune_load(c, tc) != CTCALIGN_OK) CTCA_LOG(1, "tuning cache %s not (fully) loaded", tc);
+  }
   *out = c;
   return CTCALIGN_OK;
 }
@@ -249,6 +322,10 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
     in.status = out_status + i;
     in.stride = row_stride_for(C[i]);
     const Geo g = ctx->tune.pick_pack(2 * L[i] + 1, C[i], T[i]);
+    if (!geometry_supported_pack(g.W, g.M) || !geo_ok(2 * L[i] + 1, g.W, g.M)) {
+      delete p;
+      return CTCALIGN_EINVAL;   // no compiled layout holds this trellis
+    }
     in.W = g.W;
     in.M = g.M;
     in.prio = 0;

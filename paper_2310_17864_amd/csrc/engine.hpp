@@ -72,9 +72,8 @@ __device__ __forceinline__ float sel(uint64_t m, float x, float y) {
 // acc = 2*acc + (lane's bit of m): the mask enters as the carry of one
 // v_addc_co_u32, so a backpointer bit costs one VALU op and no packing.
 __device__ __forceinline__ uint32_t shift_in(uint32_t acc, uint64_t m) {
-  uint32_t r;
-  uint64_t co;
-  asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(r), "=s"(co) : "v"(acc), "s"(m));
+  uint32_t r;   // the unused carry-out goes to VCC
+  asm("v_addc_co_u32_e64 %0, vcc, %1, %1, %2" : "=v"(r) : "v"(acc), "s"(m) : "vcc");
   return r;
 }
 

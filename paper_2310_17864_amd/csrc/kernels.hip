@@ -103,7 +103,9 @@ __device__ __forceinline__ void pack_dispatch(const Inst& in, int w, int lane, S
     case 4: run_wave<4>(in, w, lane, sy, ra, rb); break;
     case 6: run_wave<6>(in, w, lane, sy, ra, rb); break;
     case 8: run_wave<8>(in, w, lane, sy, ra, rb); break;
+    case 10: run_wave<10>(in, w, lane, sy, ra, rb); break;
     case 12: run_wave<12>(in, w, lane, sy, ra, rb); break;
+    case 14: run_wave<14>(in, w, lane, sy, ra, rb); break;
     case 16: run_wave<16>(in, w, lane, sy, ra, rb); break;
     default: __syncthreads(); break;
   }
@@ -178,7 +180,7 @@ static bool m_in(int M, const int* menu, int n) {
 
 static const int kOneMenu[] = {2, 4, 6, 8, 10, 12, 14, 16};
 static const int kLongMenu[] = {16, 24, 32, 40, 48, 56, 60, 64};
-static const int kPackMenuK[] = {2, 4, 6, 8, 12, 16};
+static const int kPackMenuK[] = {2, 4, 6, 8, 10, 12, 14, 16};
 
 bool geometry_supported_one(int W, int M) {
   if (W >= 1 && W <= 4 && m_in(M, kOneMenu, 8)) return true;
@@ -187,7 +189,7 @@ bool geometry_supported_one(int W, int M) {
 }
 
 bool geometry_supported_pack(int W, int M) {
-  return (W == 1 || W == 2 || W == 4) && m_in(M, kPackMenuK, 6);
+  return (W == 1 || W == 2 || W == 4) && m_in(M, kPackMenuK, 8);
 }
 
 hipError_t launch_one(const Inst& in, hipStream_t st) {

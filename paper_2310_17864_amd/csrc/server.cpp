@@ -362,6 +362,10 @@ int ctcalign_server_submit(ctcalign_server* s, const ctcalign_request* r, uint64
     p->g = s->ctx->tune.pick_one(S, r->C);
     p->pack = false;
   }
+  if (p->g.W == 0 || !geo_ok(S, p->g.W, p->g.M)) {
+    delete p;
+    return CTCALIGN_EINVAL;
+  }
   p->bp_bytes = round_up((size_t)bp_words(r->T, p->g.W, p->g.M) * 4, 256);
   p->pad_bytes = (r->C != p->stride || !aligned16(r->emission))
                      ? round_up((size_t)r->T * p->stride * sizeof(float), 256)

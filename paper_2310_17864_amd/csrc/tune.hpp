@@ -18,7 +18,7 @@ struct Geo {
 // M values compiled into each kernel family.
 constexpr int kMenuOne[] = {2, 4, 6, 8, 10, 12, 14, 16};          // k_one, W <= 4
 constexpr int kMenuLong[] = {16, 24, 32, 40, 48, 56, 60, 64};     // k_one_long, W <= 8
-constexpr int kMenuPack[] = {2, 4, 6, 8, 12, 16};                 // k_persistent, W in {1,2,4}
+constexpr int kMenuPack[] = {2, 4, 6, 8, 10, 12, 14, 16};         // k_persistent, W in {1,2,4}
 
 // Geometry is usable iff it covers S and the top segment holds S-1 and S-2
 // (the end-state choice reads both from one wavefront's registers).
@@ -35,6 +35,15 @@ struct TuneTable {
   int pack_target_m = 8;
   // measured overrides, indexed by S bucket (S / 64) and stride class
   std::vector<Geo> one_override[2], pack_override[2];
+
+  std::vector<Geo>& table(int kind, int C) { return kind == 0 ? one_override[cls(C)] : pack_override[cls(C)]; }
+
+  void set_range(int kind, int s_lo, int s_hi, int C, Geo g) {
+    auto& t = table(kind, C);
+    const int b1 = s_hi / kWave;
+    if ((int)t.size() <= b1) t.resize(b1 + 1, Geo{0, 0});
+    for (int b = s_lo / kWave; b <= b1; ++b) t[b] = g;
+  }
 
   void load_default(int cus) { num_cu = cus > 0 ? cus : 256; }
 
@@ -53,15 +62,13 @@ struct TuneTable {
     if (S <= 4 * kWave * 16) {
       int W = (S + kWave * one_target_m - 1) / (kWave * one_target_m);
       W = W < 1 ? 1 : (W > 4 ? 4 : W);
-      for (; W >= 1; --W) {
-        const int M = menu_up(kMenuOne, 8, (S + kWave * W - 1) / (kWave * W));
-        if (M > 0 && geo_ok(S, W, M)) return Geo{W, M};
-      }
+      for (; W >= 1; --W)
+        for (int M : kMenuOne)
+          if (geo_ok(S, W, M)) return Geo{W, M};
     }
-    for (int M : kMenuLong) {
-      const int W = (S + kWave * M - 1) / (kWave * M);
-      if (W <= 8 && geo_ok(S, W, M)) return Geo{W, M};
-    }
+    for (int M : kMenuLong)
+      for (int W = 8; W >= 1; --W)
+        if (geo_ok(S, W, M)) return Geo{W, M};
     return Geo{0, 0};
   }
 
@@ -70,15 +77,16 @@ struct TuneTable {
     const int b = S / kWave;
     const auto& ov = pack_override[cls(C)];
     if (b < (int)ov.size() && ov[b].W > 0 && geo_ok(S, ov[b].W, ov[b].M)) return ov[b];
-    for (int W : {1, 2, 4}) {
-      const int M = menu_up(kMenuPack, 6, (S + kWave * W - 1) / (kWave * W));
-      if (M > 0 && M <= pack_target_m && geo_ok(S, W, M)) return Geo{W, M};
-    }
-    for (int W : {4, 2, 1}) {
-      const int M = menu_up(kMenuPack, 6, (S + kWave * W - 1) / (kWave * W));
-      if (M > 0 && geo_ok(S, W, M)) return Geo{W, M};
-    }
-    return Geo{0, 0};
+    // fewest waves whose states per lane stay within the target, else the
+    // feasible layout with the fewest states per lane
+    for (int W : {1, 2, 4})
+      for (int M : kMenuPack)
+        if (M <= pack_target_m && geo_ok(S, W, M)) return Geo{W, M};
+    Geo best{0, 0};
+    for (int W : {4, 2, 1})
+      for (int M : kMenuPack)
+        if (geo_ok(S, W, M) && (best.W == 0 || M < best.M)) best = Geo{W, M};
+    return best;
   }
 
   int64_t max_pack_states() const { return 4 * kWave * 16; }

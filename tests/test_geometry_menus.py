@@ -1,0 +1,34 @@
+"""Every trellis size the library accepts has a compiled layout: for the
+batched kernel (S <= 4096, W in {1,2,4}) and for single launches
+(S <= 32768), some (W, M) of the menus in tune.hpp covers S with the top
+wave holding S-1 and S-2.  (A gap here once left utterances unprocessed.)"""
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TUNE = os.path.join(ROOT, "paper_2310_17864_amd", "csrc", "tune.hpp")
+
+
+def menu(name):
+    txt = open(TUNE).read()
+    m = re.search(name + r"\[\]\s*=\s*\{([^}]*)\}", txt)
+    return [int(x) for x in m.group(1).split(",")]
+
+
+def geo_ok(S, W, M):
+    seg = 64 * M
+    return W * seg >= S and (W == 1 or (W - 1) * seg + 2 <= S)
+
+
+def test_pack_menu_covers_all_sizes():
+    pack = menu("kMenuPack")
+    gaps = [S for S in range(1, 4097) if not any(geo_ok(S, W, M) for W in (1, 2, 4) for M in pack)]
+    assert gaps == []
+
+
+def test_single_menus_cover_all_sizes():
+    one, long_ = menu("kMenuOne"), menu("kMenuLong")
+    gaps = [S for S in range(1, 32769)
+            if not (any(geo_ok(S, W, M) for W in range(1, 5) for M in one)
+                    or any(geo_ok(S, W, M) for W in range(1, 9) for M in long_))]
+    assert gaps == []
