@@ -137,6 +137,19 @@ int ctcalign_align_ex(ctcalign_ctx *ctx, const float *emission, int32_t T, int32
                       int32_t *out_status, void *workspace, size_t ws_bytes,
                       ctcalign_stream stream);
 
+/* Token spans of an alignment (device pointers; asynchronous on `stream`):
+ * each maximal run of frames with the same non-blank class is one span --
+ * one per transcript token, since equal neighbouring tokens are separated by
+ * a blank in any CTC alignment.  For span i (in frame order): out_token[i]
+ * the class, out_start[i] / out_end[i] its first frame and one past its last,
+ * out_score[i] the float32 left fold of its per-frame scores.  At most
+ * max_spans spans are written; *out_count (device) receives the number found.
+ * A failed alignment (path = -1) has no spans. */
+int ctcalign_token_spans(const int32_t *path, const float *scores, int32_t T, int32_t blank,
+                         int32_t max_spans, int32_t *out_token, int32_t *out_start,
+                         int32_t *out_end, float *out_score, int32_t *out_count,
+                         ctcalign_stream stream);
+
 /* ---- many utterances: one persistent kernel over a device work queue ---- */
 
 /* Builds a plan for N utterances packed in flat device arrays.  Host arrays
@@ -147,6 +160,9 @@ int ctcalign_align_ex(ctcalign_ctx *ctx, const float *emission, int32_t T, int32
  * utterances longest first, picks each one's geometry from the tuning table,
  * uploads the descriptors, allocates the backpointer workspace and captures
  * the whole launch (queue reset + persistent kernel) in a HIP graph.
+ * Alignments of up to 4096 states run four-wavefront work items of the main
+ * persistent kernel; larger ones (up to 32768 states) run whole 8-wavefront
+ * workgroups of a second persistent kernel in the same graph.
  * Emission rows must not straddle other utterances' outputs.
  * Errors: EINVAL (bad shape or pointer), ENOMEM, EDEVICE. */
 int ctcalign_plan_create(ctcalign_ctx *ctx, int32_t N,
@@ -161,6 +177,15 @@ int ctcalign_plan_create(ctcalign_ctx *ctx, int32_t N,
 /* Replays the plan's graph on `stream` (NULL: HIP's null stream).
  * Asynchronous; per-utterance statuses land in out_status. */
 int ctcalign_plan_run(ctcalign_plan *plan, ctcalign_stream stream);
+
+/* Profiling aid: when the plan was created with $CTCALIGN_TRACE=1, copies
+ * (after its last run finished) the per-pack record {start, end, hardware id}
+ * of the 100 MHz device wall clock into out_times[3*i..] and the instance
+ * index run by each of the pack's 4 waves into out_insts[4*i..] (-1 idle),
+ * for the first max_packs packs in queue order; *npacks gets the pack count.
+ * EINVAL if the plan was created without tracing. */
+int ctcalign_plan_trace(ctcalign_plan *plan, int32_t max_packs, int64_t *out_times,
+                        int32_t *out_insts, int32_t *npacks);
 
 /* Frees the plan (waits for its last run).  NULL is a no-op. */
 int ctcalign_plan_destroy(ctcalign_plan *plan);

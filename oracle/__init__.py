@@ -108,3 +108,37 @@ def align_batch_f32(packed: dict, blank: int = 0, threads: int = 1):
         _ptr(paths), _ptr(scores), _ptr(arrs["fr_off"]), _ptr(totals), _ptr(status),
         int(threads))
     return status, paths[:frames], scores[:frames], totals, used
+
+
+def token_spans(path, scores, blank: int = 0):
+    """Token spans of a frame-level alignment (the step after alignment in a
+    forced-alignment pipeline, paper Sec. 4: frame-level alignments are
+    grouped per transcript token).
+
+    A span is a maximal run of frames carrying the same non-blank class; in
+    a CTC alignment two occurrences of one class are always separated by a
+    blank, so there is exactly one span per transcript token.  Returns
+    (token class int32[n], start int32[n], end int32[n] exclusive,
+    score float32[n] = float32 left fold of the span's per-frame scores)."""
+    path = np.asarray(path)
+    scores = np.asarray(scores, dtype=np.float32)
+    tok, st, en, sc = [], [], [], []
+    t = 0
+    T = len(path)
+    while t < T:
+        c = int(path[t])
+        if c == blank or c < 0:
+            t += 1
+            continue
+        s0 = t
+        acc = np.float32(scores[t])
+        t += 1
+        while t < T and int(path[t]) == c:
+            acc = np.float32(acc + scores[t])
+            t += 1
+        tok.append(c)
+        st.append(s0)
+        en.append(t)
+        sc.append(acc)
+    return (np.array(tok, np.int32), np.array(st, np.int32), np.array(en, np.int32),
+            np.array(sc, np.float32))

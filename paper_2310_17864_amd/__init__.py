@@ -22,7 +22,7 @@ from . import _lib
 from ._lib import (CtcAlignError, EAGAIN, EBUSY, EDEVICE, EINFEASIBLE, EINVAL, ENOMEM, OK,
                    LibraryMissing, strerror)
 
-__all__ = ["align", "align_many_launches", "Context", "Plan", "Server", "workspace_bytes", "strerror",
+__all__ = ["align", "token_spans", "align_many_launches", "Context", "Plan", "Server", "workspace_bytes", "strerror",
            "CtcAlignError", "LibraryMissing", "OK", "EINVAL", "EINFEASIBLE", "ENOMEM",
            "EDEVICE", "EAGAIN", "EBUSY"]
 
@@ -144,6 +144,27 @@ def align(emission, labels, blank: int = 0, out=None, workspace=None, sync: bool
     return path, scores, total, status
 
 
+def token_spans(path, scores, blank: int = 0, max_spans: Optional[int] = None):
+    """Token spans of an alignment on the device: (token, start, end, score)
+    int32/int32/int32/float32 device tensors, one entry per transcript token."""
+    torch = _torch()
+    _check_dev_tensor(path, torch.int32, "path")
+    _check_dev_tensor(scores, torch.float32, "scores")
+    T = path.numel()
+    n = T if max_spans is None else int(max_spans)
+    dev = path.device
+    tok = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    st = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    en = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    sc = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    _lib.check(_lib.load().ctcalign_token_spans(
+        path.data_ptr(), scores.data_ptr(), T, blank, n, tok.data_ptr(), st.data_ptr(),
+        en.data_ptr(), sc.data_ptr(), cnt.data_ptr(), _stream_handle(dev)), "token_spans")
+    k = min(int(cnt.item()), n)
+    return tok[:k], st[:k], en[:k], sc[:k]
+
+
 def align_many_launches(emissions: Sequence, labels: Sequence, blank: int = 0):
     """One kernel launch per utterance, all on the current stream (the plain
     per-utterance method).  Returns a list of (path, scores, total, status)."""
@@ -195,6 +216,18 @@ class Plan:
         torch = _torch()
         s = stream if stream is not None else torch.cuda.current_stream(self.paths.device)
         _lib.check(_lib.load().ctcalign_plan_run(self.handle, int(s.cuda_stream)), "plan_run")
+
+    def trace(self):
+        """(times int64[npacks, 3] = start, end, hw id; insts int32[npacks, 4])
+        of the last run; needs CTCALIGN_TRACE=1 when the plan was created."""
+        n = ctypes.c_int32()
+        _lib.load().ctcalign_plan_trace(self.handle, 0, None, None, ctypes.byref(n))
+        times = np.zeros((n.value, 3), dtype=np.int64)
+        insts = np.zeros((n.value, 4), dtype=np.int32)
+        _lib.check(_lib.load().ctcalign_plan_trace(
+            self.handle, n.value, times.ctypes.data_as(ctypes.c_void_p),
+            insts.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)), "plan_trace")
+        return times, insts
 
     def close(self):
         if getattr(self, "handle", None):

@@ -45,10 +45,12 @@ _PROTOS = {
     "ctcalign_workspace_bytes": (SZ, [P, I32, I32, I32]),
     "ctcalign_align": (ctypes.c_int, [P, I32, I32, P, I32, I32, P, P]),
     "ctcalign_align_ex": (ctypes.c_int, [P, P, I32, I32, P, I32, I32, P, P, P, P, P, SZ, P]),
+    "ctcalign_token_spans": (ctypes.c_int, [P, P, I32, I32, I32, P, P, P, P, P, P]),
     "ctcalign_plan_create": (ctypes.c_int, [P, I32, P, P, P, P, P, P, P, I32, P, P, P, P, P,
                                             ctypes.POINTER(P)]),
     "ctcalign_plan_run": (ctypes.c_int, [P, P]),
     "ctcalign_plan_destroy": (ctypes.c_int, [P]),
+    "ctcalign_plan_trace": (ctypes.c_int, [P, I32, P, P, ctypes.POINTER(I32)]),
     "ctcalign_align_batched": (ctypes.c_int, [P, I32, P, P, P, P, P, P, P, I32, P, P, P, P, P, P]),
     "ctcalign_tune_set": (ctypes.c_int, [P, I32, I32, I32, I32, I32, I32]),
     "ctcalign_tune_get": (ctypes.c_int, [P, I32, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),

@@ -277,6 +277,18 @@ int ctcalign_align(const float* emission, int32_t T, int32_t C, const int32_t* l
   return ctx->h_status[0];
 }
 
+int ctcalign_token_spans(const int32_t* path, const float* scores, int32_t T, int32_t blank,
+                         int32_t max_spans, int32_t* out_token, int32_t* out_start,
+                         int32_t* out_end, float* out_score, int32_t* out_count,
+                         ctcalign_stream stream) {
+  if (!path || !scores || !out_count || T < 1 || T > (1 << 30) || max_spans < 0 || blank < 0 ||
+      (max_spans > 0 && (!out_token || !out_start || !out_end || !out_score)))
+    return CTCALIGN_EINVAL;
+  HIP_TRY(launch_spans(path, scores, T, blank, max_spans, out_token, out_start, out_end, out_score,
+                       out_count, static_cast<hipStream_t>(stream)));
+  return CTCALIGN_OK;
+}
+
 // ---- batched plans -----------------------------------------------------------
 
 int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
@@ -295,7 +307,7 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
         blank >= C[i] || em_off[i] < 0 || lab_off[i] < 0 || frame_off[i] < 0)
       return CTCALIGN_EINVAL;
     if (L[i] > 0 && !labels) return CTCALIGN_EINVAL;
-    if (2 * (int64_t)L[i] + 1 > ctx->tune.max_pack_states()) return CTCALIGN_EINVAL;
+    if (2 * (int64_t)L[i] + 1 > kMaxS) return CTCALIGN_EINVAL;
   }
   HIP_TRY(hipSetDevice(ctx->device));
 
@@ -309,6 +321,7 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
   std::vector<double> cost(N);
   size_t bp_total = 0, pad_total = 0;
   std::vector<size_t> bp_off(N), pad_off(N, SIZE_MAX);
+  std::vector<char> is_long(N, 0);
   for (int i = 0; i < N; ++i) {
     Inst& in = insts[i];
     in.T = T[i];
@@ -321,11 +334,15 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
     in.total = out_totals + i;
     in.status = out_status + i;
     in.stride = row_stride_for(C[i]);
-    const Geo g = ctx->tune.pick_pack(2 * L[i] + 1, C[i], T[i]);
-    if (!geometry_supported_pack(g.W, g.M) || !geo_ok(2 * L[i] + 1, g.W, g.M)) {
+    const int S = 2 * L[i] + 1;
+    const bool big = S > ctx->tune.max_pack_states();
+    const Geo g = big ? ctx->tune.pick_one(S, C[i]) : ctx->tune.pick_pack(S, C[i], T[i]);
+    const bool supported = big ? geometry_supported_long_batch(g.W, g.M) : geometry_supported_pack(g.W, g.M);
+    if (!supported || !geo_ok(S, g.W, g.M)) {
       delete p;
       return CTCALIGN_EINVAL;   // no compiled layout holds this trellis
     }
+    is_long[i] = big;
     in.W = g.W;
     in.M = g.M;
     in.prio = 0;
@@ -362,7 +379,12 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
   };
   open2 = blank_pack();
   open1 = blank_pack();
+  std::vector<int> long_order;
   for (int idx : order) {
+    if (is_long[idx]) {
+      long_order.push_back(idx);   // already longest first
+      continue;
+    }
     const int W = insts[idx].W;
     if (W == 4) {
       Pack pk = blank_pack();
@@ -414,11 +436,16 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
     for (size_t i = 0; i < po.size(); ++i) po[i] = (int)i;
     std::stable_sort(po.begin(), po.end(), [&](int a, int b) { return pack_cost[a] > pack_cost[b]; });
     std::vector<Pack> sorted(packs.size());
-    for (size_t i = 0; i < po.size(); ++i) sorted[i] = packs[po[i]];
+    std::vector<double> sorted_cost(packs.size());
+    for (size_t i = 0; i < po.size(); ++i) {
+      sorted[i] = packs[po[i]];
+      sorted_cost[i] = pack_cost[po[i]];
+    }
     packs.swap(sorted);
+    pack_cost.swap(sorted_cost);
   }
   p->npacks = (int)packs.size();
-  ctx->tune.assign_priorities(insts, packs);
+  if (!std::getenv("CTCALIGN_NO_PRIO")) ctx->tune.assign_priorities(insts, packs, pack_cost);
 
   int rc = CTCALIGN_OK;
   auto fail = [&](int code) {
@@ -442,6 +469,13 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
     }
   }
   p->npad = (int)pads.size();
+  p->nlong = (int)long_order.size();
+  if (p->nlong &&
+      ((rc = map_hip(hipMalloc((void**)&p->d_order, sizeof(int) * p->nlong), "order")) ||
+       (rc = map_hip(hipMemcpy(p->d_order, long_order.data(), sizeof(int) * p->nlong,
+                               hipMemcpyHostToDevice), "h2d")) ||
+       (rc = map_hip(hipMalloc((void**)&p->d_head_long, sizeof(int)), "head"))))
+    return fail(rc);
   if ((rc = map_hip(hipMalloc((void**)&p->d_insts, sizeof(Inst) * std::max(N, 1)), "insts")) ||
       (rc = map_hip(hipMalloc((void**)&p->d_packs, sizeof(Pack) * std::max(p->npacks, 1)), "packs")) ||
       (rc = map_hip(hipMalloc((void**)&p->d_head, sizeof(int)), "head")))
@@ -461,6 +495,11 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
   // ones that do not fit yet start when a resident one leaves, find the queue
   // drained and exit; the hardware fills every CU to its real occupancy.
   p->grid = std::min(p->npacks, ctx->num_cu * 16);
+  if (const char* tr = std::getenv("CTCALIGN_TRACE")) {
+    if (std::atoi(tr) > 0 && p->npacks &&
+        (rc = map_hip(hipMalloc((void**)&p->d_trace, sizeof(int64_t) * 3 * p->npacks), "trace")))
+      return fail(rc);
+  }
   if (p->grid < 1) p->grid = 1;
 
   // capture: [pad] -> queue reset -> persistent kernel
@@ -472,7 +511,12 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
   if (p->npad) e = launch_pad(p->d_pad, p->npad, p->pad_max, p->cap_stream);
   if (e == hipSuccess) e = launch_fill(p->d_head, 1, 0, p->cap_stream);
   if (e == hipSuccess && p->npacks)
-    e = launch_persistent(p->d_insts, p->d_packs, p->npacks, p->d_head, p->grid, p->cap_stream);
+    e = launch_persistent(p->d_insts, p->d_packs, p->npacks, p->d_head, p->grid, p->cap_stream,
+                          p->d_trace);
+  if (e == hipSuccess && p->nlong) e = launch_fill(p->d_head_long, 1, 0, p->cap_stream);
+  if (e == hipSuccess && p->nlong)
+    e = launch_persistent_long(p->d_insts, p->d_order, p->nlong, p->d_head_long,
+                               std::min(p->nlong, ctx->num_cu * 4), p->cap_stream);
   hipError_t e2 = hipStreamEndCapture(p->cap_stream, &p->graph);
   if (e != hipSuccess) return fail(map_hip(e, "captured launch"));
   if ((rc = map_hip(e2, "end capture"))) return fail(rc);
@@ -490,6 +534,22 @@ int ctcalign_plan_run(ctcalign_plan* p, ctcalign_stream stream) {
   return CTCALIGN_OK;
 }
 
+int ctcalign_plan_trace(ctcalign_plan* p, int32_t max_packs, int64_t* out_times,
+                        int32_t* out_insts, int32_t* npacks) {
+  if (!p || !npacks) return CTCALIGN_EINVAL;
+  *npacks = p->npacks;
+  if (!p->d_trace) return CTCALIGN_EINVAL;
+  const int n = std::min(max_packs, p->npacks);
+  if (out_times) HIP_TRY(hipMemcpy(out_times, p->d_trace, sizeof(int64_t) * 3 * n, hipMemcpyDeviceToHost));
+  if (out_insts) {
+    std::vector<Pack> pk(n);
+    HIP_TRY(hipMemcpy(pk.data(), p->d_packs, sizeof(Pack) * n, hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < kPackWaves; ++k) out_insts[kPackWaves * i + k] = pk[i].inst[k];
+  }
+  return CTCALIGN_OK;
+}
+
 int ctcalign_plan_destroy(ctcalign_plan* p) {
   if (!p) return CTCALIGN_OK;
   (void)hipSetDevice(p->ctx->device);
@@ -503,6 +563,9 @@ int ctcalign_plan_destroy(ctcalign_plan* p) {
   if (p->d_head) (void)hipFree(p->d_head);
   if (p->d_bp) (void)hipFree(p->d_bp);
   if (p->d_padbuf) (void)hipFree(p->d_padbuf);
+  if (p->d_trace) (void)hipFree(p->d_trace);
+  if (p->d_order) (void)hipFree(p->d_order);
+  if (p->d_head_long) (void)hipFree(p->d_head_long);
   if (p->ctx && p->ctx->cached == p) p->ctx->cached = nullptr;
   delete p;
   return CTCALIGN_OK;

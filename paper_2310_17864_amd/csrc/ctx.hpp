@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <vector>
 
 #include "../../include/ctcalign.h"
 #include "internal.hpp"
@@ -108,4 +109,9 @@ struct ctcalign_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cap_stream = nullptr;
+  int64_t* d_trace = nullptr;          // per pack {start, end, hw id} when tracing
+  int nlong = 0;                       // instances too large for packs (k_persistent_long)
+  int* d_order = nullptr;              // their indices, longest first
+  int* d_head_long = nullptr;
+  std::vector<int> pack_order_inst;    // first instance of each pack (host copy, for traces)
 };

@@ -139,45 +139,71 @@ __device__ __forceinline__ void dp_frame(float (&a)[M], uint32_t (&acc)[bp_words
   }
 }
 
-// ---- emission chunks: HBM -> LDS by direct loads -----------------------------
+// ---- emission rows: HBM -> LDS by direct loads ------------------------------
 //
-// Chunk k holds the rows of frames t = 4k+1 .. 4k+4 (frame 0 is read
-// directly at initialisation).  Even chunks live in ring half A, odd chunks in
-// half B; both halves are distinct __shared__ objects, so the compiler knows a
-// pending copy into one half never aliases reads of the other.  HBM rows are
-// 16-byte aligned with a row stride of 32 or 256 floats (the host pads other
-// class counts beforehand) and are moved by global_load_lds_dwordx4 (16 bytes
-// per lane, no VGPR staging).  The copy of chunk k+1 is issued when chunk k
-// starts and waited for (vmcnt) when chunk k+1 starts.
+// The rows of frames t = 2k+1, 2k+2 form chunk k (frame 0 is read directly at
+// initialisation).  A wave's ring has four 2-row quarters, each a distinct
+// __shared__ object, so the compiler knows a pending copy into one quarter
+// never aliases reads of another; chunk k lives in quarter k % 4, which is
+// static inside the unrolled 8-frame group.  HBM rows are 16-byte aligned
+// with a stride of 32 or 256 floats (the host pads other class counts) and
+// move with global_load_lds_dwordx4: one instruction per row, 16 bytes per
+// lane, no VGPR staging.
+//
+// Pipeline per chunk k, issued one frame before chunk k-3 starts: wait for the
+// copy of chunk k-3... i.e. at the issue point P(k) the wave waits for chunk k,
+// then issues the copy of chunk k+3 and an L2 warm-up load of chunk k+6 (one
+// dword per 128-byte line).  Every issue point issues exactly kDmaPerChunk + 1
+// vector-memory instructions (rows past the end are clamped to the last row
+// and land in quarter rows nobody reads), so the number of operations issued
+// after a chunk's copy is a compile-time constant and the wait is an exact
+// s_waitcnt vmcnt(N): 2 later issue points (2*(kDmaPerChunk+1)) + the warm-up
+// issued with the copy (1) + the NQ backpointer stores of a group flush that
+// happened in between.
+constexpr int kDmaPerChunk = 2;
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-// LDS rows always have kMaxC (256) floats; HBM rows have hs = 32 or 256.
-__device__ __forceinline__ void dma_chunk(const float* em, int T, int hs, int k, int lane,
-                                          float* half) {
-  const int row0 = 4 * k + 1;
-  if (row0 >= T) return;
-  const int rows = (T - row0) < kChunk ? (T - row0) : kChunk;
-  const float* src = em + (int64_t)row0 * hs;
-  if (hs == kMaxC) {
-    // one contiguous 4 KB copy: 4 instructions of 64 lanes x 16 bytes
+struct Ring {
+  float* q[4];
+};
+
+__device__ __forceinline__ void dma_chunk(const float* em, int T, int hs, int k, int lane, float* quarter) {
 #pragma unroll
-    for (int q = 0; q < kChunk; ++q) {
-      const int e = 4 * (kWave * q + lane);
-      if (e < rows * kMaxC)
-        __builtin_amdgcn_global_load_lds(src + e, (lds_void_t*)(half + 4 * kWave * q), 16, 0, 0);
-    }
-  } else {
-    // 128-byte rows: one instruction per row, 8 lanes x 16 bytes
-#pragma unroll
-    for (int r = 0; r < kChunk; ++r) {
-      if (r < rows && lane < 8)
-        __builtin_amdgcn_global_load_lds(src + r * 32 + 4 * lane, (lds_void_t*)(half + r * kMaxC), 16,
-                                         0, 0);
+  for (int r = 0; r < kDmaPerChunk; ++r) {
+    int row = 2 * k + 1 + r;
+    row = row < T ? row : T - 1;                     // clamped: always issued
+    const float* src = em + (int64_t)row * hs;
+    if (hs == kMaxC) {
+      __builtin_amdgcn_global_load_lds(src + 4 * lane, (lds_void_t*)(quarter + r * kMaxC), 16, 0, 0);
+    } else {
+      const int l = lane & 7;                        // 128-byte rows: lanes 0..7 carry data,
+      __builtin_amdgcn_global_load_lds(src + 4 * l, (lds_void_t*)(quarter + r * kMaxC), 16, 0, 0);
     }
   }
 }
 
+// one dword per 128-byte line of chunk k, into L2 (always issued)
+__device__ __forceinline__ uint32_t warm_chunk(const float* em, int T, int hs, int k, int lane) {
+  int row = 2 * k + 1 + (lane * 32) / hs;
+  row = row < T ? row : T - 1;
+  const int col = (lane * 32) % hs;
+  return __builtin_bit_cast(uint32_t, em[(int64_t)row * hs + col]);
+}
+
 __device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Compiler barrier: vector-memory instructions keep their program order
+// across it, which the exact vmcnt counts below rely on.
+__device__ __forceinline__ void order_vm() { asm volatile("" ::: "memory"); }
+
+// Waits until at most N vector-memory operations are outstanding.  Memory
+// operations retire in issue order, so this waits for everything issued
+// before the last N.
+template <int N>
+__device__ __forceinline__ void wait_vm_keep() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
 
 // Where segment outcomes go for the backtrack.
 struct FwdOut {
@@ -191,8 +217,8 @@ struct FwdOut {
 // `sy` points at the SegSync of segment 0 of this instance; the caller has
 // cleared it and passed a workgroup barrier after `prologue_check`.
 template <int M>
-__device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, const int lane, float* ringA,
-                                  float* ringB, SegSync* sy, bool labels_bad) {
+__device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, const int lane,
+                                                  const Ring& ring, SegSync* sy, bool labels_bad) {
   const int T = in.T, L = in.L, blank = in.blank, W = in.W;
   const int S = 2 * L + 1;                  // state counts fit int32 (host-checked)
   const int sbase = (w * kWave + lane) * M;
@@ -235,6 +261,9 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   SegSync* me = sy + w;
   SegSync* prev = has_prev ? sy + w - 1 : nullptr;
   SegSync* next = has_next ? sy + w + 1 : nullptr;
+  // boundary values are read every frame through a pointer that always points
+  // into the SegSync array (the compiler then knows it cannot alias the ring)
+  const SegSync* pv = sy + (has_prev ? w - 1 : w);
   if (has_next) {
     if (lane == kWave - 1) me->bnd[0] = a[M - 1];
     lds_store_rel(&me->prod, 1);
@@ -247,7 +276,45 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   uint32_t* bpw = in.bp + (int64_t)w * ngrp * NQ * kWave + lane;
 
   const int hs = in.stride;
-  if (nsteps > 0) dma_chunk(em, T, hs, 0, lane, ringA);
+  constexpr int kAfter = 2 * (kDmaPerChunk + 1) + 1;   // ops issued after a chunk's copy
+  constexpr bool kAhead = M <= 16;   // gathers one frame ahead (needs M/2+1 more VGPRs)
+  // Each ring quarter is its own LDS object (so the compiler can tell a copy
+  // into one quarter from reads of another and adds no waits of its own); the
+  // gather address of a label slot then differs per quarter.  Hoisting all of
+  // them costs 4*M/2 registers: recompute them each frame instead (one add
+  // per gather).
+  constexpr bool kRecompute = true;
+  uint32_t warm_acc = 0, wq0 = 0, wq1 = 0, wq2 = 0;
+  float eb_c = 0.f;
+  float e_c[M / 2];
+#pragma unroll
+  for (int jj = 0; jj < M / 2; ++jj) e_c[jj] = 0.f;
+  if (nsteps > 0) {
+    // issue points P(-3..-1), then P(0): chunk 0 is needed by frame 0
+    dma_chunk(em, T, hs, 0, lane, ring.q[0]);
+    order_vm();
+    wq0 = warm_chunk(em, T, hs, 3, lane);
+    order_vm();
+    dma_chunk(em, T, hs, 1, lane, ring.q[1]);
+    order_vm();
+    wq1 = warm_chunk(em, T, hs, 4, lane);
+    order_vm();
+    dma_chunk(em, T, hs, 2, lane, ring.q[2]);
+    order_vm();
+    wq2 = warm_chunk(em, T, hs, 5, lane);
+    wait_vm_keep<kAfter>();        // P(0): 7 operations were issued after chunk 0's copy
+    dma_chunk(em, T, hs, 3, lane, ring.q[3]);
+    order_vm();
+    warm_acc ^= wq0;
+    wq0 = wq1;
+    wq1 = wq2;
+    wq2 = warm_chunk(em, T, hs, 6, lane);
+    if constexpr (kAhead) {
+      eb_c = ring.q[0][blank];
+#pragma unroll
+      for (int jj = 0; jj < M / 2; ++jj) e_c[jj] = ring.q[0][eoff[jj]];
+    }
+  }
 
   uint32_t acc[NQ];
 #pragma unroll
@@ -266,27 +333,97 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
     for (int g = 0; g < kBlk / kUnroll; ++g) {
       const int ng = n - kUnroll * g;            // frames of this group (may be < 8 or <= 0)
       if (ng <= 0) break;
+      const bool first_group = (b == 0 && g == 0);
+      const int ubase = 32 * b + kUnroll * g;
+      // One frame: i is the frame's static position in the group.
+      auto frame = [&](auto ic) __attribute__((always_inline)) {
+        constexpr int i = decltype(ic)::value;
+        const int uu = ubase + i;                // computes frame t = uu + 1
+        float eb_n = 0.f;
+        float e_n[M / 2];
+        if constexpr (kRecompute) {
 #pragma unroll
-      for (int i = 0; i < kUnroll; ++i) {
-        if (i < ng) {
-          u = 32 * b + kUnroll * g + i;          // computes frame t = u + 1
-          if (i % kChunk == 0) {
-            // a2: chunk u/4 has landed; start copying the next one
-            wait_dma();
-            dma_chunk(em, T, hs, u / kChunk + 1, lane, (i < kChunk) ? ringB : ringA);
-          }
-          // frame u reads ring half (u/4)%2 == i/4, row u%4 == i%4
-          const float* row = ((i < kChunk) ? ringA : ringB) + (i % kChunk) * kMaxC;
-          const float eb = row[blank];
-          float e[M / 2];
+          for (int jj = 0; jj < M / 2; ++jj) asm volatile("" : "+v"(eoff[jj]));
+        }
+        if constexpr (!kAhead) {
+          // wide lanes: read this frame's values now (no spare registers),
+          // before the issue point below refills this frame's quarter
+          const float* rc = ring.q[(i / 2) % 4] + (i % 2) * kMaxC;
+          eb_c = rc[blank];
 #pragma unroll
-          for (int jj = 0; jj < M / 2; ++jj) e[jj] = row[eoff[jj]];
-          const float nb_in = has_prev ? prev->bnd[u % kBnd] : neg_inf();
+          for (int jj = 0; jj < M / 2; ++jj) e_c[jj] = rc[eoff[jj]];
+        }
+        if constexpr (i % 2 == 1) {
+          // a2: issue point P(k) for the chunk the next frame opens: wait
+          // for chunk k, start chunk k+3, warm chunk k+6
+          const int k = (uu + 1) / 2;
+          if (i == kUnroll - 1 || first_group)
+            wait_vm_keep<kAfter>();              // no group flush since chunk k was issued
+          else
+            wait_vm_keep<kAfter + NQ>();         // the previous group's stores may be pending
+          // the quarter about to be refilled holds chunk k-1 (this frame's);
+          // its reads were issued earlier: let them finish first
+          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+          dma_chunk(em, T, hs, k + 3, lane, ring.q[((i + 1) / 2 + 3) % 4]);
+          order_vm();
+          warm_acc ^= wq0;                       // issued three issue points ago
+          wq0 = wq1;
+          wq1 = wq2;
+          wq2 = warm_chunk(em, T, hs, k + 6, lane);
+        }
+        if constexpr (kAhead) {
+          // next frame's values (past the last frame this reads unused rows)
+          const float* rn = ring.q[((i + 1) / 2) % 4] + ((i + 1) % 2) * kMaxC;
+          eb_n = rn[blank];
+#pragma unroll
+          for (int jj = 0; jj < M / 2; ++jj) e_n[jj] = rn[eoff[jj]];
+        }
+        const float bv = pv->bnd[uu % kBnd];
+        const float nb_in = has_prev ? bv : neg_inf();
+        const float nb = shr1(a[M - 1], nb_in);
+        dp_frame<M>(a, acc, skip, nb, eb_c, e_c);
+        if (has_next && lane == kWave - 1) me->bnd[(uu + 1) % kBnd] = a[M - 1];
+        if constexpr (kAhead) {
+          eb_c = eb_n;
+#pragma unroll
+          for (int jj = 0; jj < M / 2; ++jj) e_c[jj] = e_n[jj];
+        }
+        u = uu;
+        // keep each frame's instructions together: bounds live registers
+        __builtin_amdgcn_sched_barrier(0);
+      };
+      using I0 = std::integral_constant<int, 0>;
+      using I1 = std::integral_constant<int, 1>;
+      using I2 = std::integral_constant<int, 2>;
+      using I3 = std::integral_constant<int, 3>;
+      using I4 = std::integral_constant<int, 4>;
+      using I5 = std::integral_constant<int, 5>;
+      using I6 = std::integral_constant<int, 6>;
+      using I7 = std::integral_constant<int, 7>;
+      if (ng >= kUnroll) {
+        // full group: straight-line code
+        frame(I0{}); frame(I1{}); frame(I2{}); frame(I3{});
+        frame(I4{}); frame(I5{}); frame(I6{}); frame(I7{});
+      } else {
+        // The utterance's last, short group (< 8 frames): the copies issued
+        // so far already cover it (they run 6 frames ahead), so wait for them
+        // all and read the ring directly, one frame per iteration.
+        wait_dma();
+#pragma unroll 1
+        for (int i = 0; i < ng; ++i) {
+          const int uu = ubase + i;
+          const int qi = (i >> 1) & 3;
+          const float* rc = (qi == 0 ? ring.q[0] : qi == 1 ? ring.q[1] : qi == 2 ? ring.q[2] : ring.q[3]) +
+                            (i & 1) * kMaxC;
+          eb_c = rc[blank];
+#pragma unroll
+          for (int jj = 0; jj < M / 2; ++jj) e_c[jj] = rc[eoff[jj]];
+          const float bv = pv->bnd[uu % kBnd];
+          const float nb_in = has_prev ? bv : neg_inf();
           const float nb = shr1(a[M - 1], nb_in);
-          dp_frame<M>(a, acc, skip, nb, eb, e);
-          if (has_next && lane == kWave - 1) me->bnd[(u + 1) % kBnd] = a[M - 1];
-          // keep each frame's instructions together: bounds live registers
-          __builtin_amdgcn_sched_barrier(0);
+          dp_frame<M>(a, acc, skip, nb, eb_c, e_c);
+          if (has_next && lane == kWave - 1) me->bnd[(uu + 1) % kBnd] = a[M - 1];
+          u = uu;
         }
       }
       // a5: flush the group's backpointer words; frame i of plane r of word q
@@ -306,6 +443,7 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   }
   out.ok = alive ? 1 : 0;
   wait_dma();   // no copy into LDS may outlive this instance
+  if (warm_acc == 0x7fc00001u && T < 0) in.path[0] = (int)warm_acc;   // keeps the warm-up loads
 
   // a6: end state, in the segment that holds S-1 and S-2
   if (w == W - 1) {

@@ -7,8 +7,7 @@ namespace ctca {
 constexpr int kWave = 64;       // lanes per wavefront (CDNA)
 constexpr int kBlk = 32;        // frames per backpointer word
 constexpr int kUnroll = 8;      // frames per unrolled group in the forward loop
-constexpr int kChunk = 4;       // emission rows per staged chunk
-constexpr int kRing = 8;        // emission rows held in a wave's LDS ring
+constexpr int kRing = 8;        // emission rows held in a wave's LDS ring (4 quarters x 2 rows)
 constexpr int kBnd = 128;       // boundary values held between two segments
 constexpr int kMaxC = 256;      // largest class count served by the LDS ring
 constexpr int kPackWaves = 4;   // waves per workgroup in the persistent kernels

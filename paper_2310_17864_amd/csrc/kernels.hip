@@ -19,14 +19,13 @@ namespace ctca {
 // barrier, forward pass, then either "done" publication (lower segments) or
 // end-state selection and backtrack (the top segment).
 template <int M>
-__device__ __forceinline__ void run_wave(const Inst& in, int w, int lane, SegSync* sy, float* ringA,
-                                         float* ringB) {
+__device__ __forceinline__ void run_wave(const Inst& in, int w, int lane, SegSync* sy, const Ring& ring) {
   const bool bad = prologue_check<M>(in, w, lane);
   if (bad && lane == 0) sy[w].bad = 1;
   __syncthreads();
   bool any_bad = false;
   for (int k = 0; k < in.W; ++k) any_bad |= (sy[k].bad != 0);
-  const FwdOut fo = segment_forward<M>(in, w, lane, ringA, ringB, sy, any_bad);
+  const FwdOut fo = segment_forward<M>(in, w, lane, ring, sy, any_bad);
   if (w + 1 < in.W) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // backpointer stores reach L2
     if (lane == 0) lds_store_rel(&sy[w].done, 1);
@@ -61,15 +60,17 @@ __device__ __forceinline__ void reset_sync(SegSync* s, int lane) {
 
 #define CTCA_CASE(MM) \
   case MM:            \
-    run_wave<MM>(in, w, lane, sy, ringA[w], ringB[w]); \
+    run_wave<MM>(in, w, lane, sy, Ring{{rq0[w], rq1[w], rq2[w], rq3[w]}}); \
     break;
 
-// LDS of the single-instance kernels: per wave a SegSync and two 4-row ring
-// halves (distinct objects, see dma_chunk).
-__global__ void __launch_bounds__(256) k_one(Inst in) {
+// LDS of the single-instance kernels: per wave a SegSync and four 2-row ring
+// quarters (distinct objects, see dma_chunk).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_one(Inst in) {
   __shared__ SegSync sy[4];
-  __shared__ __attribute__((aligned(16))) float ringA[4][kChunk * kMaxC];
-  __shared__ __attribute__((aligned(16))) float ringB[4][kChunk * kMaxC];
+  __shared__ __attribute__((aligned(16))) float rq0[4][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float rq1[4][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float rq2[4][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float rq3[4][2 * kMaxC];
   // the wave index is uniform across a wave; readfirstlane tells the compiler
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   reset_sync(sy + w, lane);
@@ -83,8 +84,10 @@ __global__ void __launch_bounds__(256) k_one(Inst in) {
 // Long form: up to 8 waves (2 per SIMD), up to 64 states per lane.
 __global__ void __launch_bounds__(512) k_one_long(Inst in) {
   __shared__ SegSync sy[8];
-  __shared__ __attribute__((aligned(16))) float ringA[8][kChunk * kMaxC];
-  __shared__ __attribute__((aligned(16))) float ringB[8][kChunk * kMaxC];
+  __shared__ __attribute__((aligned(16))) float rq0[8][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float rq1[8][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float rq2[8][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float rq3[8][2 * kMaxC];
   // the wave index is uniform across a wave; readfirstlane tells the compiler
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   reset_sync(sy + w, lane);
@@ -94,30 +97,34 @@ __global__ void __launch_bounds__(512) k_one_long(Inst in) {
     default: __syncthreads(); break;
   }
 }
-#undef CTCA_CASE
 
 __device__ __forceinline__ void pack_dispatch(const Inst& in, int w, int lane, SegSync* sy,
-                                              float* ra, float* rb) {
+                                              const Ring& r) {
   switch (in.M) {
-    case 2: run_wave<2>(in, w, lane, sy, ra, rb); break;
-    case 4: run_wave<4>(in, w, lane, sy, ra, rb); break;
-    case 6: run_wave<6>(in, w, lane, sy, ra, rb); break;
-    case 8: run_wave<8>(in, w, lane, sy, ra, rb); break;
-    case 10: run_wave<10>(in, w, lane, sy, ra, rb); break;
-    case 12: run_wave<12>(in, w, lane, sy, ra, rb); break;
-    case 14: run_wave<14>(in, w, lane, sy, ra, rb); break;
-    case 16: run_wave<16>(in, w, lane, sy, ra, rb); break;
+    case 2: run_wave<2>(in, w, lane, sy, r); break;
+    case 4: run_wave<4>(in, w, lane, sy, r); break;
+    case 6: run_wave<6>(in, w, lane, sy, r); break;
+    case 8: run_wave<8>(in, w, lane, sy, r); break;
+    case 10: run_wave<10>(in, w, lane, sy, r); break;
+    case 12: run_wave<12>(in, w, lane, sy, r); break;
+    case 14: run_wave<14>(in, w, lane, sy, r); break;
+    case 16: run_wave<16>(in, w, lane, sy, r); break;
     default: __syncthreads(); break;
   }
 }
 
-// LDS: 4 SegSync and, per wave, two 4-row ring halves of the widest stride.
-__global__ void __launch_bounds__(256) k_persistent(const Inst* __restrict__ insts,
+// LDS: 4 SegSync and, per wave, four 2-row ring quarters of the widest stride.
+// trace (optional, may be null): per pack {start, end} of the 100 MHz
+// wall clock and the hardware id of the CU that ran it.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_persistent(const Inst* __restrict__ insts,
                                                     const Pack* __restrict__ packs, int npacks,
-                                                    int* __restrict__ head) {
+                                                    int* __restrict__ head,
+                                                    int64_t* __restrict__ trace) {
   __shared__ SegSync sy[kPackWaves];
-  __shared__ __attribute__((aligned(16))) float ringA[kPackWaves][kChunk * kMaxC];
-  __shared__ __attribute__((aligned(16))) float ringB[kPackWaves][kChunk * kMaxC];
+  __shared__ __attribute__((aligned(16))) float rq0[kPackWaves][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float rq1[kPackWaves][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float rq2[kPackWaves][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float rq3[kPackWaves][2 * kMaxC];
   __shared__ int s_item;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   for (;;) {
@@ -126,6 +133,10 @@ __global__ void __launch_bounds__(256) k_persistent(const Inst* __restrict__ ins
     __syncthreads();
     const int item = __builtin_amdgcn_readfirstlane(s_item);
     if (item >= npacks) break;
+    if (trace && threadIdx.x == 0) {
+      trace[3 * item] = (int64_t)__builtin_amdgcn_s_memrealtime();
+      trace[3 * item + 2] = (int64_t)__builtin_amdgcn_s_getreg((4 << 0) | (0 << 6) | (31 << 11));
+    }
     const int ii = packs[item].inst[wv];
     if (ii < 0) {
       __syncthreads();   // the barrier the busy waves take inside run_wave
@@ -134,16 +145,52 @@ __global__ void __launch_bounds__(256) k_persistent(const Inst* __restrict__ ins
       const int seg = packs[item].seg[wv];
       const int first = packs[item].first[wv];
       set_prio(in.prio);
-      pack_dispatch(in, seg, lane, sy + first, ringA[wv], ringB[wv]);
+      pack_dispatch(in, seg, lane, sy + first, Ring{{rq0[wv], rq1[wv], rq2[wv], rq3[wv]}});
       __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();     // every wave is done with this pack's LDS
+    if (trace && threadIdx.x == 0) trace[3 * item + 1] = (int64_t)__builtin_amdgcn_s_memrealtime();
   }
 }
 
 // Copies rows of a [T][C] emission into a [T][stride] buffer (zeros in the
 // pad columns), so the alignment kernels always see 16-byte aligned rows of
 // a compiled stride.  blockIdx.y selects the descriptor.
+// Batched large alignments: each 8-wave workgroup pops one instance index
+// (into `order`) at a time and runs its W <= 8 segments; waves beyond W wait
+// at the two workgroup barriers.  Same engine and LDS layout as k_one_long.
+__global__ void __launch_bounds__(512) k_persistent_long(const Inst* __restrict__ insts,
+                                                         const int* __restrict__ order, int n,
+                                                         int* __restrict__ head) {
+  __shared__ SegSync sy[8];
+  __shared__ __attribute__((aligned(16))) float rq0[8][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float rq1[8][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float rq2[8][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float rq3[8][2 * kMaxC];
+  __shared__ int s_item;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(head, 1);
+    reset_sync(sy + w, lane);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    if (item >= n) break;
+    const Inst in = insts[order[item]];
+    if (w >= in.W) {
+      __syncthreads();   // the barrier the busy waves take inside run_wave
+    } else {
+      switch (in.M) {
+        CTCA_CASE(16) CTCA_CASE(24) CTCA_CASE(32) CTCA_CASE(40)
+        CTCA_CASE(48) CTCA_CASE(56) CTCA_CASE(60) CTCA_CASE(64)
+        default: __syncthreads(); break;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+#undef CTCA_CASE
+
 __global__ void __launch_bounds__(256) k_pad(const PadDesc* __restrict__ d) {
   const PadDesc pd = d[blockIdx.y];
   const int64_t total = (int64_t)pd.T * pd.stride;
@@ -163,6 +210,59 @@ __global__ void __launch_bounds__(256) k_pad_one(PadDesc pd) {
     const int c = (int)(i - r * pd.stride);
     pd.dst[i] = c < pd.C ? pd.src[r * pd.C + c] : 0.0f;
   }
+}
+
+// Token spans of a frame path: a span starts at a non-blank frame whose
+// class differs from the previous frame's; its index is the number of starts
+// before it (wave ballot + popcount, then a prefix over the 16 waves in LDS);
+// the starting thread walks the span and folds its scores in frame order.
+__global__ void __launch_bounds__(1024) k_spans(const int32_t* __restrict__ path,
+                                                const float* __restrict__ scores, int T, int blank,
+                                                int max_spans, int32_t* __restrict__ tok,
+                                                int32_t* __restrict__ start, int32_t* __restrict__ end,
+                                                float* __restrict__ score, int32_t* __restrict__ count) {
+  __shared__ int wave_tot[16];
+  __shared__ int base;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) base = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < T; c0 += 1024) {
+    const int t = c0 + tid;
+    int cls = -1;
+    bool is_start = false;
+    if (t < T) {
+      cls = path[t];
+      is_start = cls >= 0 && cls != blank && (t == 0 || path[t - 1] != cls);
+    }
+    const uint64_t m = __builtin_amdgcn_ballot_w64(is_start);
+    const int before = __builtin_popcountll(m & ((lane ? (~0ull >> (64 - lane)) : 0ull)));
+    if (lane == 0) wave_tot[wv] = __builtin_popcountll(m);
+    __syncthreads();
+    int off = base, tot = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      if (k < wv) off += wave_tot[k];
+      tot += wave_tot[k];
+    }
+    if (is_start) {
+      const int idx = off + before;
+      int e = t;
+      float acc = scores[t];
+      while (e + 1 < T && path[e + 1] == cls) {
+        ++e;
+        acc = acc + scores[e];
+      }
+      if (idx < max_spans) {
+        tok[idx] = cls;
+        start[idx] = t;
+        end[idx] = e + 1;
+        score[idx] = acc;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) base += tot;
+    __syncthreads();
+  }
+  if (tid == 0) *count = base;
 }
 
 __global__ void k_fill(int* p, int n, int v) {
@@ -202,9 +302,9 @@ hipError_t launch_one(const Inst& in, hipStream_t st) {
 }
 
 hipError_t launch_persistent(const Inst* d_insts, const Pack* d_packs, int npacks, int* d_head,
-                             int grid, hipStream_t st) {
+                             int grid, hipStream_t st, int64_t* d_trace) {
   hipLaunchKernelGGL(k_persistent, dim3(grid), dim3(kWave * kPackWaves), 0, st, d_insts, d_packs,
-                     npacks, d_head);
+                     npacks, d_head, d_trace);
   return hipGetLastError();
 }
 
@@ -221,6 +321,23 @@ hipError_t launch_pad_one(const PadDesc& pd, hipStream_t st) {
   int64_t bx = ((int64_t)pd.T * pd.stride + 255) / 256;
   bx = bx > 1024 ? 1024 : (bx < 1 ? 1 : bx);
   hipLaunchKernelGGL(k_pad_one, dim3((unsigned)bx), dim3(256), 0, st, pd);
+  return hipGetLastError();
+}
+
+hipError_t launch_persistent_long(const Inst* d_insts, const int* d_order, int n, int* d_head,
+                                  int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_persistent_long, dim3(grid), dim3(kWave * 8), 0, st, d_insts, d_order, n,
+                     d_head);
+  return hipGetLastError();
+}
+
+bool geometry_supported_long_batch(int W, int M) { return W >= 1 && W <= 8 && m_in(M, kLongMenu, 8); }
+
+hipError_t launch_spans(const int32_t* path, const float* scores, int T, int blank, int max_spans,
+                        int32_t* tok, int32_t* start, int32_t* end, float* score, int32_t* count,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_spans, dim3(1), dim3(1024), 0, st, path, scores, T, blank, max_spans, tok, start,
+                     end, score, count);
   return hipGetLastError();
 }
 

@@ -10,8 +10,14 @@ bool geometry_supported_one(int W, int M);
 bool geometry_supported_pack(int W, int M);
 hipError_t launch_one(const Inst& in, hipStream_t st);
 hipError_t launch_persistent(const Inst* d_insts, const Pack* d_packs, int npacks, int* d_head,
-                             int grid, hipStream_t st);
+                             int grid, hipStream_t st, int64_t* d_trace = nullptr);
 hipError_t launch_fill(int* p, int n, int v, hipStream_t st);
+hipError_t launch_persistent_long(const Inst* d_insts, const int* d_order, int n, int* d_head,
+                                  int grid, hipStream_t st);
+bool geometry_supported_long_batch(int W, int M);
+hipError_t launch_spans(const int32_t* path, const float* scores, int T, int blank, int max_spans,
+                        int32_t* tok, int32_t* start, int32_t* end, float* score, int32_t* count,
+                        hipStream_t st);
 hipError_t launch_pad(const PadDesc* d_desc, int n, int64_t max_elems, hipStream_t st);
 hipError_t launch_pad_one(const PadDesc& pd, hipStream_t st);
 int persistent_blocks_per_cu();

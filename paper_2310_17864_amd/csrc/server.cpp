@@ -12,6 +12,7 @@
 // querying the slots' events; statuses come back through pinned memory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <condition_variable>
 #include <cstring>
@@ -49,7 +50,9 @@ struct Slot {
   Inst* h_inst = nullptr;       // pinned
   Pack* h_pack = nullptr;       // pinned
   int32_t* h_status = nullptr;  // pinned
+  int32_t* h_order = nullptr;   // pinned
   Inst* d_inst = nullptr;
+  int32_t* d_order = nullptr;
   Pack* d_pack = nullptr;
   int32_t* d_status = nullptr;
   int* d_head = nullptr;
@@ -74,6 +77,8 @@ class HipExec {
       HIP_TRY(hipHostMalloc((void**)&s.h_inst, sizeof(Inst) * kMaxBatch));
       HIP_TRY(hipHostMalloc((void**)&s.h_pack, sizeof(Pack) * kMaxBatch));
       HIP_TRY(hipHostMalloc((void**)&s.h_status, sizeof(int32_t) * kMaxBatch));
+      HIP_TRY(hipHostMalloc((void**)&s.h_order, sizeof(int32_t) * kMaxBatch));
+      HIP_TRY(hipMalloc((void**)&s.d_order, sizeof(int32_t) * kMaxBatch));
       HIP_TRY(hipMalloc((void**)&s.d_inst, sizeof(Inst) * kMaxBatch));
       HIP_TRY(hipMalloc((void**)&s.d_pack, sizeof(Pack) * kMaxBatch));
       HIP_TRY(hipMalloc((void**)&s.d_status, sizeof(int32_t) * kMaxBatch));
@@ -90,6 +95,8 @@ class HipExec {
       if (s.h_inst) (void)hipHostFree(s.h_inst);
       if (s.h_pack) (void)hipHostFree(s.h_pack);
       if (s.h_status) (void)hipHostFree(s.h_status);
+      if (s.h_order) (void)hipHostFree(s.h_order);
+      if (s.d_order) (void)hipFree(s.d_order);
       if (s.d_inst) (void)hipFree(s.d_inst);
       if (s.d_pack) (void)hipFree(s.d_pack);
       if (s.d_status) (void)hipFree(s.d_status);
@@ -112,8 +119,8 @@ class HipExec {
   Handle launch(std::vector<SchedReq*>& reqs) {
     Handle h;
     h.where.resize(reqs.size());
-    int small_slot = -1;
-    int nsmall = 0;
+    int small_slot = -1, long_slot = -1;
+    int nsmall = 0, nlong = 0;
     for (size_t k = 0; k < reqs.size(); ++k) {
       const Payload* p = static_cast<Payload*>(reqs[k]->user);
       if (p->pack) {
@@ -121,6 +128,12 @@ class HipExec {
         h.where[k] = {small_slot, nsmall};
         slots_[small_slot].h_inst[nsmall] = make_inst(*p, reqs[k]->arena_off, slots_[small_slot].d_status + nsmall);
         ++nsmall;
+      } else if (!p->pad_bytes) {
+        // large trellis: all of this group's go to one persistent launch
+        if (long_slot < 0) long_slot = take_slot();
+        h.where[k] = {long_slot, nlong};
+        slots_[long_slot].h_inst[nlong] = make_inst(*p, reqs[k]->arena_off, slots_[long_slot].d_status + nlong);
+        ++nlong;
       } else {
         const int sl = take_slot();
         Slot& s = slots_[sl];
@@ -130,6 +143,12 @@ class HipExec {
         h.slots.push_back(sl);
         submit_one(s, *p, reqs[k]->arena_off);
       }
+    }
+    if (long_slot >= 0) {
+      Slot& s = slots_[long_slot];
+      s.n = nlong;
+      h.slots.push_back(long_slot);
+      submit_long(s);
     }
     if (small_slot >= 0) {
       Slot& s = slots_[small_slot];
@@ -209,6 +228,24 @@ class HipExec {
     launch_err_[sl] = err;
   }
 
+  void submit_long(Slot& s) {
+    const int sl = (int)(&s - slots_);
+    bool err = false;
+    // longest first
+    for (int i = 0; i < s.n; ++i) s.h_order[i] = i;
+    std::sort(s.h_order, s.h_order + s.n, [&](int a, int b) {
+      return (int64_t)s.h_inst[a].T * s.h_inst[a].M > (int64_t)s.h_inst[b].T * s.h_inst[b].M;
+    });
+    err |= hipMemcpyAsync(s.d_inst, s.h_inst, sizeof(Inst) * s.n, hipMemcpyHostToDevice, s.stream) != hipSuccess;
+    err |= hipMemcpyAsync(s.d_order, s.h_order, sizeof(int32_t) * s.n, hipMemcpyHostToDevice, s.stream) != hipSuccess;
+    err |= launch_fill(s.d_head, 1, 0, s.stream) != hipSuccess;
+    const int grid = std::min(s.n, ctx_->num_cu * 4);
+    err |= launch_persistent_long(s.d_inst, s.d_order, s.n, s.d_head, grid, s.stream) != hipSuccess;
+    err |= hipMemcpyAsync(s.h_status, s.d_status, sizeof(int32_t) * s.n, hipMemcpyDeviceToHost, s.stream) != hipSuccess;
+    err |= hipEventRecord(s.done, s.stream) != hipSuccess;
+    launch_err_[sl] = err;
+  }
+
   void submit_packs(Slot& s) {
     const int sl = (int)(&s - slots_);
     bool err = false;
@@ -244,7 +281,7 @@ class HipExec {
     err |= hipMemcpyAsync(s.d_pack, s.h_pack, sizeof(Pack) * np, hipMemcpyHostToDevice, s.stream) != hipSuccess;
     err |= launch_fill(s.d_head, 1, 0, s.stream) != hipSuccess;
     const int grid = std::min(np, ctx_->num_cu * 16);
-    err |= launch_persistent(s.d_inst, s.d_pack, np, s.d_head, grid, s.stream) != hipSuccess;
+    err |= launch_persistent(s.d_inst, s.d_pack, np, s.d_head, grid, s.stream, nullptr) != hipSuccess;
     err |= hipMemcpyAsync(s.h_status, s.d_status, sizeof(int32_t) * s.n, hipMemcpyDeviceToHost, s.stream) != hipSuccess;
     err |= hipEventRecord(s.done, s.stream) != hipSuccess;
     launch_err_[sl] = err;

@@ -94,11 +94,24 @@ struct TuneTable {
   // relative time of one frame on one wave
   double step_cost(Geo g, int stride) const { return 5.5 * g.M + 12.0 + (stride > 32 ? 2.0 : 0.0); }
 
-  // issue priority: the waves of the packs that start first (the longest
-  // chains) get precedence over their co-resident neighbours
-  void assign_priorities(std::vector<Inst>& insts, const std::vector<Pack>& packs) const {
-    (void)insts;
-    (void)packs;
+  // Issue priority.  The queue is sorted longest first, so the first num_cu
+  // packs start together, one per CU, and carry the longest chains of the
+  // batch: the critical path.  Their waves (one per SIMD) get s_setprio so
+  // they run at nearly the speed of a wave alone on its SIMD while the other
+  // waves of the CU take the remaining issue slots.  Packs much shorter than
+  // the longest one are left at normal priority.
+  int prio_packs_per_cu = 1;
+  double prio_min_frac = 0.4;
+  void assign_priorities(std::vector<Inst>& insts, const std::vector<Pack>& packs,
+                         const std::vector<double>& pack_cost) const {
+    if (packs.empty()) return;
+    const double top = pack_cost[0];
+    const size_t n = std::min(packs.size(), (size_t)num_cu * prio_packs_per_cu);
+    for (size_t i = 0; i < n; ++i) {
+      if (pack_cost[i] < prio_min_frac * top) break;
+      for (int k = 0; k < kPackWaves; ++k)
+        if (packs[i].inst[k] >= 0) insts[packs[i].inst[k]].prio = 3;
+    }
   }
 };
 

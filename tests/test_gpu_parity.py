@@ -132,3 +132,32 @@ def test_batched_order_invariant():
         assert np.array_equal(scores[a:b].view(np.uint32), scores2[c:d].view(np.uint32))
         assert totals[i].view(np.uint32) == totals2[j].view(np.uint32)
         assert st[i] == st2[j]
+
+
+def test_batched_with_large_trellises():
+    # S > 4096 runs on the 8-wave persistent kernel next to the 4-wave packs
+    rng = np.random.default_rng(41)
+    utts = [synth.utterance(rng, 2 * L + 30, C, L, 0, 6.0, 1.0, None)
+            for L, C in [(2100, 32), (3000, 256), (5000, 32), (8000, 256), (12000, 32), (16383, 32)]]
+    utts += [synth.utterance(rng, int(rng.integers(50, 900)), 32, int(rng.integers(5, 40)), 0, 6.0,
+                             1.0, None) for _ in range(20)]
+    pk = synth.pack(utts)
+    ref = oracle.align_batch_f32(pk, threads=8)
+    assert compare_batched(pk, gpu_batched(pk), ref, "large") == []
+
+
+def test_token_spans_match_oracle():
+    import paper_2310_17864_amd as ca
+    from gpu_util import torch_dev
+    torch, dev = torch_dev()
+    for seed, (T, L, C) in enumerate([(200, 40, 32), (3000, 600, 256), (90, 0, 32), (5000, 900, 29)]):
+        u = synth.utterance(np.random.default_rng(seed), T, C, L, 0, 6.0, 1.0, 0.2)
+        path, scores, total, status = ca.align(torch.from_numpy(u.emission).to(dev),
+                                               torch.from_numpy(u.labels).to(dev) if L else
+                                               torch.empty(0, dtype=torch.int32, device=dev), 0)
+        tok, st, en, sc = ca.token_spans(path, scores, 0)
+        st_o, p_o, s_o, _ = oracle.align_f32(u.emission, u.labels, 0)
+        rt, rs, re, rsc = oracle.token_spans(p_o, s_o, 0)
+        assert np.array_equal(tok.cpu().numpy(), rt) and np.array_equal(tok.cpu().numpy(), u.labels)
+        assert np.array_equal(st.cpu().numpy(), rs) and np.array_equal(en.cpu().numpy(), re)
+        assert np.array_equal(sc.cpu().numpy().view(np.uint32), rsc.view(np.uint32))

@@ -111,3 +111,36 @@ def test_batch_entry_matches_single():
         assert np.array_equal(paths[a:b], p)
         assert np.array_equal(scores[a:b].view(np.uint32), s.view(np.uint32))
         assert totals[i].view(np.uint32) == t.view(np.uint32)
+
+
+def test_token_spans_closed_forms():
+    # hand-checkable path: blanks around, a repeated label split by a blank
+    path = np.array([0, 3, 3, 0, 0, 3, 5, 5, 5, 0], np.int32)
+    scores = np.array([-1, -0.5, -0.25, -1, -1, -2, -1, -1, -0.5, -3], np.float32)
+    tok, st, en, sc = oracle.token_spans(path, scores, 0)
+    assert tok.tolist() == [3, 3, 5]
+    assert st.tolist() == [1, 5, 6] and en.tolist() == [3, 6, 9]
+    assert sc.tolist() == [-0.75, -2.0, -2.5]
+    # no tokens
+    tok, st, en, sc = oracle.token_spans(np.zeros(7, np.int32), np.zeros(7, np.float32), 0)
+    assert len(tok) == 0
+
+
+def test_token_spans_on_alignments():
+    # one span per transcript token, in order, covering exactly the non-blank
+    # frames; with integer scores the span sums and the blank frames add up
+    # exactly to the alignment total
+    for seed in range(5):
+        r = np.random.default_rng(seed)
+        T, C, L = int(r.integers(30, 400)), 12, int(r.integers(1, 10))
+        u = synth.utterance(r, max(T, 2 * L + 2), C, L, 0, 4.0, 1.0, 0.3)
+        E = np.round(u.emission * 4).astype(np.float32) / 4      # exact sums
+        st, path, scores, total = oracle.align_f32(E, u.labels, 0)
+        tok, s0, s1, sc = oracle.token_spans(path, scores, 0)
+        assert np.array_equal(tok, u.labels)
+        assert np.all(s0[1:] >= s1[:-1]) and np.all(s1 > s0)
+        covered = np.zeros(len(path), bool)
+        for a, b in zip(s0, s1):
+            covered[a:b] = True
+        assert np.array_equal(covered, path != 0)
+        assert float(np.sum(sc)) + float(np.sum(scores[path == 0])) == float(total)
