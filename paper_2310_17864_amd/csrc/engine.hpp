@@ -142,30 +142,46 @@ __device__ __forceinline__ void dp_frame(float (&a)[M], uint32_t (&acc)[bp_words
 // ---- emission rows: HBM -> LDS by direct loads ------------------------------
 //
 // The rows of frames t = 2k+1, 2k+2 form chunk k (frame 0 is read directly at
-// initialisation).  A wave's ring has four 2-row quarters, each a distinct
-// __shared__ object, so the compiler knows a pending copy into one quarter
-// never aliases reads of another; chunk k lives in quarter k % 4, which is
-// static inside the unrolled 8-frame group.  HBM rows are 16-byte aligned
-// with a stride of 32 or 256 floats (the host pads other class counts) and
-// move with global_load_lds_dwordx4: one instruction per row, 16 bytes per
-// lane, no VGPR staging.
+// initialisation).  A wave's ring holds four 2-row quarters; chunk k lives in
+// quarter k % 4, which is static inside the unrolled 8-frame group.  HBM rows
+// are 16-byte aligned with a stride of 32 or 256 floats (the host pads other
+// class counts) and move with global_load_lds_dwordx4: one instruction per
+// row, 16 bytes per lane, no VGPR staging.
 //
-// Pipeline per chunk k, issued one frame before chunk k-3 starts: wait for the
-// copy of chunk k-3... i.e. at the issue point P(k) the wave waits for chunk k,
-// then issues the copy of chunk k+3 and an L2 warm-up load of chunk k+6 (one
-// dword per 128-byte line).  Every issue point issues exactly kDmaPerChunk + 1
-// vector-memory instructions (rows past the end are clamped to the last row
-// and land in quarter rows nobody reads), so the number of operations issued
-// after a chunk's copy is a compile-time constant and the wait is an exact
-// s_waitcnt vmcnt(N): 2 later issue points (2*(kDmaPerChunk+1)) + the warm-up
-// issued with the copy (1) + the NQ backpointer stores of a group flush that
-// happened in between.
+// The copies are issued from inline assembly: the compiler does not see them
+// as LDS writes, so it adds no waits of its own before ring reads, and the
+// kernel orders them itself.  Each row copy is one vector-memory operation and
+// loads complete in issue order; stores (the backpointer words) may complete
+// out of order relative to loads, so no wait counts on them: waiting until at
+// most N operations are outstanding, N = the number of row copies issued after
+// the target, also waits out every store issued after the target.
+//
+// Schedule: at the end of the last frame of chunk k-1 (an odd frame of the
+// group) wait for chunk k, then copy chunk k+3 into the quarter chunk k-1 has
+// just vacated.  The copies of chunks k+1 and k+2 follow chunk k's, so the
+// wait is vmcnt(4).
 constexpr int kDmaPerChunk = 2;
+constexpr int kDmaAfter = 2 * kDmaPerChunk;
 typedef __attribute__((address_space(3))) void lds_void_t;
 
+// A wave's emission ring: kRing rows of kMaxC floats in LDS.
 struct Ring {
-  float* q[4];
+  float* base;
 };
+
+__device__ __forceinline__ float* ring_quarter(const Ring& r, int q) { return r.base + q * 2 * kMaxC; }
+
+// One 16-byte-per-lane copy of global memory into LDS at lds_dst + 16*lane.
+// M0 holds the LDS address; one wait state separates its write from the copy.
+__device__ __forceinline__ void dma_row(const float* src, float* lds_dst) {
+  const uint32_t l = (uint32_t)(uintptr_t)(lds_void_t*)lds_dst;
+  asm volatile(
+      "s_mov_b32 m0, %0\n\t"
+      "s_nop 0\n\t"
+      "global_load_lds_dwordx4 %1, off" ::"s"(l),
+      "v"(src)
+      : "memory", "m0");
+}
 
 __device__ __forceinline__ void dma_chunk(const float* em, int T, int hs, int k, int lane, float* quarter) {
 #pragma unroll
@@ -173,32 +189,15 @@ __device__ __forceinline__ void dma_chunk(const float* em, int T, int hs, int k,
     int row = 2 * k + 1 + r;
     row = row < T ? row : T - 1;                     // clamped: always issued
     const float* src = em + (int64_t)row * hs;
-    if (hs == kMaxC) {
-      __builtin_amdgcn_global_load_lds(src + 4 * lane, (lds_void_t*)(quarter + r * kMaxC), 16, 0, 0);
-    } else {
-      const int l = lane & 7;                        // 128-byte rows: lanes 0..7 carry data,
-      __builtin_amdgcn_global_load_lds(src + 4 * l, (lds_void_t*)(quarter + r * kMaxC), 16, 0, 0);
-    }
+    // 1 KB rows: 64 lanes x 16 bytes; 128-byte rows: lanes 0..7 carry the
+    // data, the others repeat it into the unused part of the LDS row
+    dma_row(src + 4 * (hs == kMaxC ? lane : (lane & 7)), quarter + r * kMaxC);
   }
-}
-
-// one dword per 128-byte line of chunk k, into L2 (always issued)
-__device__ __forceinline__ uint32_t warm_chunk(const float* em, int T, int hs, int k, int lane) {
-  int row = 2 * k + 1 + (lane * 32) / hs;
-  row = row < T ? row : T - 1;
-  const int col = (lane * 32) % hs;
-  return __builtin_bit_cast(uint32_t, em[(int64_t)row * hs + col]);
 }
 
 __device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// Compiler barrier: vector-memory instructions keep their program order
-// across it, which the exact vmcnt counts below rely on.
-__device__ __forceinline__ void order_vm() { asm volatile("" ::: "memory"); }
-
-// Waits until at most N vector-memory operations are outstanding.  Memory
-// operations retire in issue order, so this waits for everything issued
-// before the last N.
+// Waits until at most N vector-memory operations are outstanding.
 template <int N>
 __device__ __forceinline__ void wait_vm_keep() {
   static_assert(N >= 0 && N < 64, "vmcnt range");
@@ -276,44 +275,12 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   uint32_t* bpw = in.bp + (int64_t)w * ngrp * NQ * kWave + lane;
 
   const int hs = in.stride;
-  constexpr int kAfter = 2 * (kDmaPerChunk + 1) + 1;   // ops issued after a chunk's copy
-  constexpr bool kAhead = M <= 16;   // gathers one frame ahead (needs M/2+1 more VGPRs)
-  // Each ring quarter is its own LDS object (so the compiler can tell a copy
-  // into one quarter from reads of another and adds no waits of its own); the
-  // gather address of a label slot then differs per quarter.  Hoisting all of
-  // them costs 4*M/2 registers: recompute them each frame instead (one add
-  // per gather).
-  constexpr bool kRecompute = true;
-  uint32_t warm_acc = 0, wq0 = 0, wq1 = 0, wq2 = 0;
-  float eb_c = 0.f;
-  float e_c[M / 2];
-#pragma unroll
-  for (int jj = 0; jj < M / 2; ++jj) e_c[jj] = 0.f;
   if (nsteps > 0) {
-    // issue points P(-3..-1), then P(0): chunk 0 is needed by frame 0
-    dma_chunk(em, T, hs, 0, lane, ring.q[0]);
-    order_vm();
-    wq0 = warm_chunk(em, T, hs, 3, lane);
-    order_vm();
-    dma_chunk(em, T, hs, 1, lane, ring.q[1]);
-    order_vm();
-    wq1 = warm_chunk(em, T, hs, 4, lane);
-    order_vm();
-    dma_chunk(em, T, hs, 2, lane, ring.q[2]);
-    order_vm();
-    wq2 = warm_chunk(em, T, hs, 5, lane);
-    wait_vm_keep<kAfter>();        // P(0): 7 operations were issued after chunk 0's copy
-    dma_chunk(em, T, hs, 3, lane, ring.q[3]);
-    order_vm();
-    warm_acc ^= wq0;
-    wq0 = wq1;
-    wq1 = wq2;
-    wq2 = warm_chunk(em, T, hs, 6, lane);
-    if constexpr (kAhead) {
-      eb_c = ring.q[0][blank];
-#pragma unroll
-      for (int jj = 0; jj < M / 2; ++jj) e_c[jj] = ring.q[0][eoff[jj]];
-    }
+    dma_chunk(em, T, hs, 0, lane, ring_quarter(ring, 0));
+    dma_chunk(em, T, hs, 1, lane, ring_quarter(ring, 1));
+    dma_chunk(em, T, hs, 2, lane, ring_quarter(ring, 2));
+    wait_vm_keep<kDmaAfter>();     // chunk 0 has landed
+    dma_chunk(em, T, hs, 3, lane, ring_quarter(ring, 3));
   }
 
   uint32_t acc[NQ];
@@ -333,60 +300,29 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
     for (int g = 0; g < kBlk / kUnroll; ++g) {
       const int ng = n - kUnroll * g;            // frames of this group (may be < 8 or <= 0)
       if (ng <= 0) break;
-      const bool first_group = (b == 0 && g == 0);
       const int ubase = 32 * b + kUnroll * g;
       // One frame: i is the frame's static position in the group.
       auto frame = [&](auto ic) __attribute__((always_inline)) {
         constexpr int i = decltype(ic)::value;
         const int uu = ubase + i;                // computes frame t = uu + 1
-        float eb_n = 0.f;
-        float e_n[M / 2];
-        if constexpr (kRecompute) {
+        const float* rc = ring_quarter(ring, (i / 2) % 4) + (i % 2) * kMaxC;
+        const float eb = rc[blank];
+        float e[M / 2];
 #pragma unroll
-          for (int jj = 0; jj < M / 2; ++jj) asm volatile("" : "+v"(eoff[jj]));
-        }
-        if constexpr (!kAhead) {
-          // wide lanes: read this frame's values now (no spare registers),
-          // before the issue point below refills this frame's quarter
-          const float* rc = ring.q[(i / 2) % 4] + (i % 2) * kMaxC;
-          eb_c = rc[blank];
-#pragma unroll
-          for (int jj = 0; jj < M / 2; ++jj) e_c[jj] = rc[eoff[jj]];
-        }
-        if constexpr (i % 2 == 1) {
-          // a2: issue point P(k) for the chunk the next frame opens: wait
-          // for chunk k, start chunk k+3, warm chunk k+6
-          const int k = (uu + 1) / 2;
-          if (i == kUnroll - 1 || first_group)
-            wait_vm_keep<kAfter>();              // no group flush since chunk k was issued
-          else
-            wait_vm_keep<kAfter + NQ>();         // the previous group's stores may be pending
-          // the quarter about to be refilled holds chunk k-1 (this frame's);
-          // its reads were issued earlier: let them finish first
-          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-          dma_chunk(em, T, hs, k + 3, lane, ring.q[((i + 1) / 2 + 3) % 4]);
-          order_vm();
-          warm_acc ^= wq0;                       // issued three issue points ago
-          wq0 = wq1;
-          wq1 = wq2;
-          wq2 = warm_chunk(em, T, hs, k + 6, lane);
-        }
-        if constexpr (kAhead) {
-          // next frame's values (past the last frame this reads unused rows)
-          const float* rn = ring.q[((i + 1) / 2) % 4] + ((i + 1) % 2) * kMaxC;
-          eb_n = rn[blank];
-#pragma unroll
-          for (int jj = 0; jj < M / 2; ++jj) e_n[jj] = rn[eoff[jj]];
-        }
+        for (int jj = 0; jj < M / 2; ++jj) e[jj] = rc[eoff[jj]];
         const float bv = pv->bnd[uu % kBnd];
         const float nb_in = has_prev ? bv : neg_inf();
         const float nb = shr1(a[M - 1], nb_in);
-        dp_frame<M>(a, acc, skip, nb, eb_c, e_c);
+        dp_frame<M>(a, acc, skip, nb, eb, e);
         if (has_next && lane == kWave - 1) me->bnd[(uu + 1) % kBnd] = a[M - 1];
-        if constexpr (kAhead) {
-          eb_c = eb_n;
-#pragma unroll
-          for (int jj = 0; jj < M / 2; ++jj) e_c[jj] = e_n[jj];
+        if constexpr (i % 2 == 1) {
+          // a2: chunk k-1 is consumed; wait for chunk k (the next frame's)
+          // and refill chunk k-1's quarter with chunk k+3 once its reads
+          // have completed
+          const int k = (uu + 1) / 2;
+          wait_vm_keep<kDmaAfter>();
+          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+          dma_chunk(em, T, hs, k + 3, lane, ring_quarter(ring, (i / 2) % 4));
         }
         u = uu;
         // keep each frame's instructions together: bounds live registers
@@ -412,16 +348,15 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
 #pragma unroll 1
         for (int i = 0; i < ng; ++i) {
           const int uu = ubase + i;
-          const int qi = (i >> 1) & 3;
-          const float* rc = (qi == 0 ? ring.q[0] : qi == 1 ? ring.q[1] : qi == 2 ? ring.q[2] : ring.q[3]) +
-                            (i & 1) * kMaxC;
-          eb_c = rc[blank];
+          const float* rc = ring_quarter(ring, (i >> 1) & 3) + (i & 1) * kMaxC;
+          const float eb = rc[blank];
+          float e[M / 2];
 #pragma unroll
-          for (int jj = 0; jj < M / 2; ++jj) e_c[jj] = rc[eoff[jj]];
+          for (int jj = 0; jj < M / 2; ++jj) e[jj] = rc[eoff[jj]];
           const float bv = pv->bnd[uu % kBnd];
           const float nb_in = has_prev ? bv : neg_inf();
           const float nb = shr1(a[M - 1], nb_in);
-          dp_frame<M>(a, acc, skip, nb, eb_c, e_c);
+          dp_frame<M>(a, acc, skip, nb, eb, e);
           if (has_next && lane == kWave - 1) me->bnd[(uu + 1) % kBnd] = a[M - 1];
           u = uu;
         }
@@ -443,7 +378,6 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   }
   out.ok = alive ? 1 : 0;
   wait_dma();   // no copy into LDS may outlive this instance
-  if (warm_acc == 0x7fc00001u && T < 0) in.path[0] = (int)warm_acc;   // keeps the warm-up loads
 
   // a6: end state, in the segment that holds S-1 and S-2
   if (w == W - 1) {

@@ -60,17 +60,14 @@ __device__ __forceinline__ void reset_sync(SegSync* s, int lane) {
 
 #define CTCA_CASE(MM) \
   case MM:            \
-    run_wave<MM>(in, w, lane, sy, Ring{{rq0[w], rq1[w], rq2[w], rq3[w]}}); \
+    run_wave<MM>(in, w, lane, sy, Ring{ring[w]}); \
     break;
 
-// LDS of the single-instance kernels: per wave a SegSync and four 2-row ring
-// quarters (distinct objects, see dma_chunk).
+// LDS of the single-instance kernels: per wave a SegSync and an 8-row
+// emission ring.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_one(Inst in) {
   __shared__ SegSync sy[4];
-  __shared__ __attribute__((aligned(16))) float rq0[4][2 * kMaxC];
-  __shared__ __attribute__((aligned(16))) float rq1[4][2 * kMaxC];
-  __shared__ __attribute__((aligned(16))) float rq2[4][2 * kMaxC];
-  __shared__ __attribute__((aligned(16))) float rq3[4][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float ring[4][kRing * kMaxC];
   // the wave index is uniform across a wave; readfirstlane tells the compiler
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   reset_sync(sy + w, lane);
@@ -84,10 +81,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 // Long form: up to 8 waves (2 per SIMD), up to 64 states per lane.
 __global__ void __launch_bounds__(512) k_one_long(Inst in) {
   __shared__ SegSync sy[8];
-  __shared__ __attribute__((aligned(16))) float rq0[8][2 * kMaxC];
-  __shared__ __attribute__((aligned(16))) float rq1[8][2 * kMaxC];
-  __shared__ __attribute__((aligned(16))) float rq2[8][2 * kMaxC];
-  __shared__ __attribute__((aligned(16))) float rq3[8][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float ring[8][kRing * kMaxC];
   // the wave index is uniform across a wave; readfirstlane tells the compiler
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   reset_sync(sy + w, lane);
@@ -113,7 +107,7 @@ __device__ __forceinline__ void pack_dispatch(const Inst& in, int w, int lane, S
   }
 }
 
-// LDS: 4 SegSync and, per wave, four 2-row ring quarters of the widest stride.
+// LDS: 4 SegSync and, per wave, an 8-row emission ring of the widest stride.
 // trace (optional, may be null): per pack {start, end} of the 100 MHz
 // wall clock and the hardware id of the CU that ran it.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_persistent(const Inst* __restrict__ insts,
@@ -121,10 +115,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                                                     int* __restrict__ head,
                                                     int64_t* __restrict__ trace) {
   __shared__ SegSync sy[kPackWaves];
-  __shared__ __attribute__((aligned(16))) float rq0[kPackWaves][2 * kMaxC];
-  __shared__ __attribute__((aligned(16))) float rq1[kPackWaves][2 * kMaxC];
-  __shared__ __attribute__((aligned(16))) float rq2[kPackWaves][2 * kMaxC];
-  __shared__ __attribute__((aligned(16))) float rq3[kPackWaves][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float ring[kPackWaves][kRing * kMaxC];
   __shared__ int s_item;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   for (;;) {
@@ -145,7 +136,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       const int seg = packs[item].seg[wv];
       const int first = packs[item].first[wv];
       set_prio(in.prio);
-      pack_dispatch(in, seg, lane, sy + first, Ring{{rq0[wv], rq1[wv], rq2[wv], rq3[wv]}});
+      pack_dispatch(in, seg, lane, sy + first, Ring{ring[wv]});
       __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();     // every wave is done with this pack's LDS
@@ -163,10 +154,7 @@ __global__ void __launch_bounds__(512) k_persistent_long(const Inst* __restrict_
                                                          const int* __restrict__ order, int n,
                                                          int* __restrict__ head) {
   __shared__ SegSync sy[8];
-  __shared__ __attribute__((aligned(16))) float rq0[8][2 * kMaxC];
-  __shared__ __attribute__((aligned(16))) float rq1[8][2 * kMaxC];
-  __shared__ __attribute__((aligned(16))) float rq2[8][2 * kMaxC];
-  __shared__ __attribute__((aligned(16))) float rq3[8][2 * kMaxC];
+  __shared__ __attribute__((aligned(16))) float ring[8][kRing * kMaxC];
   __shared__ int s_item;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   for (;;) {
