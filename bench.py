@@ -124,11 +124,54 @@ def bench_plain(steps, warmup):
             "bit_exact": bool(exact), "workload": "64 utterances T~U{500..1500} C=32 L=T/5"}
 
 
+def copy_calibration(mb):
+    """A plain device-to-device copy of `mb` MiB (3 launches): under
+    rocprofv3 --pmc its FETCH_SIZE / WRITE_SIZE give the counters' scale."""
+    import torch
+    n = (mb << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)      # one elementwise kernel: reads mb MiB, writes mb MiB
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 copies of {mb} MiB")
+    del a, b
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persistent_batched4096_traffic.txt")
+
+
+def kernel_source_hash():
+    from paper_2310_17864_amd.profile_summary import kernel_source_hash as h
+    return h()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the persistent kernel from the committed
+    rocprofv3 counter summary, scaled by the copy calibration; None when the
+    summary is missing or was taken on other kernel sources."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.split("=", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_hash") != kernel_source_hash():
+            return None
+        cb = float(kv["copy_bytes"])
+        f = float(kv["fetch_kb"]) * cb / float(kv["copy_fetch_kb"])
+        w = float(kv["write_kb"]) * cb / float(kv["copy_write_kb"])
+        return f + w
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def run_batched(args):
     import oracle
     from paper_2310_17864_amd import synth
     t = time.time()
-    pk = synth.packed_parallel("batched", args.n, workers=cpu_threads(), t_lo=100, t_hi=6000)
+    pk = synth.packed_parallel("batched", args.n, workers=args.gen_workers, t_lo=100, t_hi=6000)
     log(f"generated {args.n} utterances, {pk['frames']} frames in {time.time() - t:.1f}s")
 
     # CPU oracle on the host cores: the bit-exact reference and the baseline
@@ -205,7 +248,7 @@ def run_batched(args):
         "plain_per_utterance": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "roofline": {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": hbm / HBM_PEAK_GBS, "traffic": None,
+                     "frac": hbm / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_persistent (graph: queue reset + persistent kernel)",
                      "bytes_per_launch": bytes_alg},
         "alu": {"achieved_ops_per_s": alu, "peak_ops_per_s": VALU_PEAK_OPS,
@@ -280,7 +323,7 @@ def run_serving(args, pk=None):
     from paper_2310_17864_amd import synth
     t = time.time()
     if pk is None:
-        pk = synth.packed_parallel("serving", args.pool, workers=cpu_threads(), t_lo=100,
+        pk = synth.packed_parallel("serving", args.pool, workers=args.gen_workers, t_lo=100,
                                    t_hi=30000, seed=5)
     log(f"serving pool: {args.pool} utterances, {pk['frames']} frames in {time.time() - t:.1f}s")
     times, idx = synth.poisson_arrivals(args.rate, args.serve_seconds, args.pool, seed=5)
@@ -420,6 +463,10 @@ def main():
     ap.add_argument("--budget-gb", type=int, default=64)
     ap.add_argument("--serve-warmup", type=float, default=5.0)
     ap.add_argument("--serve-check", type=int, default=64)
+    ap.add_argument("--gen-workers", type=int, default=cpu_threads(),
+                    help="processes generating the synthetic workload (1 under a profiler)")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
@@ -430,9 +477,11 @@ def main():
         # generated before any GPU work: the generator forks worker processes
         from paper_2310_17864_amd import synth
         t = time.time()
-        pk_serve = synth.packed_parallel("serving", args.pool, workers=cpu_threads(), t_lo=100,
+        pk_serve = synth.packed_parallel("serving", args.pool, workers=args.gen_workers, t_lo=100,
                                          t_hi=30000, seed=5)
         log(f"serving pool generated in {time.time() - t:.1f}s")
+    if args.copy_calibration_mb > 0:
+        copy_calibration(args.copy_calibration_mb)
     if args.workload == "batched":
         out = run_batched(args)
         if args.serve_seconds > 0:

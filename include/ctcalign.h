@@ -160,9 +160,11 @@ int ctcalign_token_spans(const int32_t *path, const float *scores, int32_t T, in
  * utterances longest first, picks each one's geometry from the tuning table,
  * uploads the descriptors, allocates the backpointer workspace and captures
  * the whole launch (queue reset + persistent kernel) in a HIP graph.
- * Alignments of up to 4096 states run four-wavefront work items of the main
- * persistent kernel; larger ones (up to 32768 states) run whole 8-wavefront
- * workgroups of a second persistent kernel in the same graph.
+ * Alignments of up to 4096 states run as work items of the main persistent
+ * kernel (a 4-wavefront workgroup runs one 4-wave alignment, or two 2-wave
+ * or four 1-wave ones); larger ones (up to 32768 states) run
+ * whole 8-wavefront workgroups of a second persistent kernel in the same
+ * graph.
  * Emission rows must not straddle other utterances' outputs.
  * Errors: EINVAL (bad shape or pointer), ENOMEM, EDEVICE. */
 int ctcalign_plan_create(ctcalign_ctx *ctx, int32_t N,

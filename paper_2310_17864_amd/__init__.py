@@ -28,6 +28,8 @@ __all__ = ["align", "token_spans", "align_many_launches", "Context", "Plan", "Se
 
 _contexts: Dict[int, "Context"] = {}
 
+PACK_WAVES = 4   # wavefronts per work item of the batched kernel
+
 
 def _torch():
     import torch
@@ -223,7 +225,7 @@ class Plan:
         n = ctypes.c_int32()
         _lib.load().ctcalign_plan_trace(self.handle, 0, None, None, ctypes.byref(n))
         times = np.zeros((n.value, 3), dtype=np.int64)
-        insts = np.zeros((n.value, 4), dtype=np.int32)
+        insts = np.zeros((n.value, PACK_WAVES), dtype=np.int32)
         _lib.check(_lib.load().ctcalign_plan_trace(
             self.handle, n.value, times.ctypes.data_as(ctypes.c_void_p),
             insts.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)), "plan_trace")

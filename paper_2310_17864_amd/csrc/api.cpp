@@ -361,13 +361,10 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
   for (int i = 0; i < N; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
 
-  // packs of 4 waves: W=4 alone, W=2 in pairs, W=1 in fours (neighbours in
-  // cost order, so a pack's waves finish at similar times)
+  // packs of kPackWaves waves: kPackWaves / W alignments of W waves each,
+  // neighbours in cost order, so a pack's waves finish at similar times
   std::vector<Pack> packs;
   std::vector<double> pack_cost;
-  Pack open2{}, open1{};
-  int n2 = 0, n1 = 0;
-  double c2 = 0, c1 = 0;
   auto blank_pack = [] {
     Pack pk;
     for (int k = 0; k < kPackWaves; ++k) {
@@ -377,60 +374,37 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
     }
     return pk;
   };
-  open2 = blank_pack();
-  open1 = blank_pack();
+  Pack open[kPackWaves + 1];
+  int nopen[kPackWaves + 1] = {};
+  double copen[kPackWaves + 1] = {};
+  for (int W = 1; W <= kPackWaves; ++W) open[W] = blank_pack();
   std::vector<int> long_order;
   for (int idx : order) {
     if (is_long[idx]) {
       long_order.push_back(idx);   // already longest first
       continue;
     }
-    const int W = insts[idx].W;
-    if (W == 4) {
-      Pack pk = blank_pack();
-      for (int k = 0; k < 4; ++k) {
-        pk.inst[k] = idx;
-        pk.seg[k] = (int16_t)k;
-        pk.first[k] = 0;
-      }
-      packs.push_back(pk);
-      pack_cost.push_back(cost[idx]);
-    } else if (W == 2) {
-      for (int k = 0; k < 2; ++k) {
-        open2.inst[2 * n2 + k] = idx;
-        open2.seg[2 * n2 + k] = (int16_t)k;
-        open2.first[2 * n2 + k] = (int16_t)(2 * n2);
-      }
-      c2 = std::max(c2, cost[idx]);
-      if (++n2 == 2) {
-        packs.push_back(open2);
-        pack_cost.push_back(c2);
-        open2 = blank_pack();
-        n2 = 0;
-        c2 = 0;
-      }
-    } else {
-      open1.inst[n1] = idx;
-      open1.seg[n1] = 0;
-      open1.first[n1] = (int16_t)n1;
-      c1 = std::max(c1, cost[idx]);
-      if (++n1 == 4) {
-        packs.push_back(open1);
-        pack_cost.push_back(c1);
-        open1 = blank_pack();
-        n1 = 0;
-        c1 = 0;
-      }
+    const int W = insts[idx].W;    // 1, 2, 4 or 8 (geometry_supported_pack)
+    const int m = nopen[W];
+    for (int k = 0; k < W; ++k) {
+      open[W].inst[m * W + k] = idx;
+      open[W].seg[m * W + k] = (int16_t)k;
+      open[W].first[m * W + k] = (int16_t)(m * W);
+    }
+    copen[W] = std::max(copen[W], cost[idx]);
+    if (++nopen[W] == kPackWaves / W) {
+      packs.push_back(open[W]);
+      pack_cost.push_back(copen[W]);
+      open[W] = blank_pack();
+      nopen[W] = 0;
+      copen[W] = 0;
     }
   }
-  if (n2) {
-    packs.push_back(open2);
-    pack_cost.push_back(c2);
-  }
-  if (n1) {
-    packs.push_back(open1);
-    pack_cost.push_back(c1);
-  }
+  for (int W = 1; W <= kPackWaves; ++W)
+    if (nopen[W]) {
+      packs.push_back(open[W]);
+      pack_cost.push_back(copen[W]);
+    }
   {
     std::vector<int> po(packs.size());
     for (size_t i = 0; i < po.size(); ++i) po[i] = (int)i;

@@ -110,7 +110,7 @@ __device__ __forceinline__ void pack_dispatch(const Inst& in, int w, int lane, S
 // LDS: 4 SegSync and, per wave, an 8-row emission ring of the widest stride.
 // trace (optional, may be null): per pack {start, end} of the 100 MHz
 // wall clock and the hardware id of the CU that ran it.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_persistent(const Inst* __restrict__ insts,
+__global__ void __launch_bounds__(kWave * kPackWaves) __attribute__((amdgpu_waves_per_eu(4))) k_persistent(const Inst* __restrict__ insts,
                                                     const Pack* __restrict__ packs, int npacks,
                                                     int* __restrict__ head,
                                                     int64_t* __restrict__ trace) {
@@ -277,7 +277,7 @@ bool geometry_supported_one(int W, int M) {
 }
 
 bool geometry_supported_pack(int W, int M) {
-  return (W == 1 || W == 2 || W == 4) && m_in(M, kPackMenuK, 8);
+  return (W == 1 || W == 2 || W == 4 || W == 8) && W <= kPackWaves && m_in(M, kPackMenuK, 8);
 }
 
 hipError_t launch_one(const Inst& in, hipStream_t st) {

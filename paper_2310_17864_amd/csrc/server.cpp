@@ -249,9 +249,10 @@ class HipExec {
   void submit_packs(Slot& s) {
     const int sl = (int)(&s - slots_);
     bool err = false;
-    // packs: W=4 alone, W=2 in pairs, W=1 in fours (padded emissions never
-    // come here: they take a single launch with its pad kernel)
-    std::vector<int> by_w[5];
+    // packs of kPackWaves waves: kPackWaves / W instances of W waves each
+    // (padded emissions never come here: they take a single launch with its
+    // pad kernel)
+    std::vector<int> by_w[kPackWaves + 1];
     for (int i = 0; i < s.n; ++i) by_w[s.h_inst[i].W].push_back(i);
     int np = 0;
     auto blank_pack = [] {
@@ -263,7 +264,7 @@ class HipExec {
       }
       return pk;
     };
-    for (int W : {4, 2, 1}) {
+    for (int W : {8, 4, 2, 1}) {
       const auto& v = by_w[W];
       const int per = kPackWaves / W;
       for (size_t i = 0; i < v.size(); i += per) {

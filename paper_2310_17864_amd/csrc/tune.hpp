@@ -79,16 +79,18 @@ struct TuneTable {
     if (b < (int)ov.size() && ov[b].W > 0 && geo_ok(S, ov[b].W, ov[b].M)) return ov[b];
     // fewest waves whose states per lane stay within the target, else the
     // feasible layout with the fewest states per lane
-    for (int W : {1, 2, 4})
+    for (int W : {1, 2, 4, 8})
       for (int M : kMenuPack)
-        if (M <= pack_target_m && geo_ok(S, W, M)) return Geo{W, M};
+        if (W <= kPackWaves && M <= pack_target_m && geo_ok(S, W, M)) return Geo{W, M};
     Geo best{0, 0};
-    for (int W : {4, 2, 1})
+    for (int W : {8, 4, 2, 1})
       for (int M : kMenuPack)
-        if (geo_ok(S, W, M) && (best.W == 0 || M < best.M)) best = Geo{W, M};
+        if (W <= kPackWaves && geo_ok(S, W, M) && (best.W == 0 || M < best.M)) best = Geo{W, M};
     return best;
   }
 
+  // Largest trellis for the pack kernel: every S up to 4 * 64 * 16 has a
+  // pack layout (W <= 4 covers them all; W = 8 layouts leave gaps above).
   int64_t max_pack_states() const { return 4 * kWave * 16; }
 
   // relative time of one frame on one wave

@@ -1,0 +1,112 @@
+"""Condenses rocprofv3 output into the short text summaries kept under
+profiles/ (kernel durations, HBM traffic per dispatch).
+
+    python -m paper_2310_17864_amd.profile_summary stats <dir> <out.txt> --command "..."
+    python -m paper_2310_17864_amd.profile_summary traffic <fetch_dir> <write_dir> <out.txt> \
+        --copy-bytes N --command "..."
+
+`stats` reads the kernel_stats.csv of a `--kernel-trace --stats` run.
+`traffic` reads the counter_collection.csv of two `--pmc FETCH_SIZE` /
+`--pmc WRITE_SIZE` runs, takes the median per-dispatch value of the
+persistent alignment kernel and of the calibration copy kernel (an
+elementwise negation of copy_bytes bytes), and records both with the hash of
+the kernel sources they were taken on.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import statistics
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["engine.hpp", "internal.hpp", "kernels.hip", "tune.hpp", "api.cpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _find(d: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def stats(d: str, out: str, command: str, top: int = 12) -> None:
+    rows = list(csv.DictReader(open(_find(d, "kernel_stats.csv"))))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# rocprofv3 --kernel-trace --stats summary",
+             f"# command: {command}",
+             f"# kernel sources: {kernel_source_hash()}",
+             f"{'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_%':>8}  kernel"]
+    for r in rows[:top]:
+        lines.append(f"{int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
+                     f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
+                     f"{float(r['Percentage']):8.2f}  {r['Name'][:110]}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def _per_dispatch(path: str, counter: str, pattern: str):
+    vals = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter or pattern not in r["Kernel_Name"]:
+            continue
+        d = r["Dispatch_Id"]
+        vals[d] = vals.get(d, 0.0) + float(r["Counter_Value"])
+    if not vals:
+        raise SystemExit(f"no {counter} rows for kernels matching {pattern!r} in {path}")
+    return statistics.median(vals.values()), len(vals)
+
+
+def traffic(fetch_dir: str, write_dir: str, out: str, copy_bytes: int, command: str,
+            kernel: str = "k_persistent", copy_kernel: str = "neg") -> None:
+    fpath, wpath = _find(fetch_dir, "counter_collection.csv"), _find(write_dir, "counter_collection.csv")
+    fk, nf = _per_dispatch(fpath, "FETCH_SIZE", kernel)
+    wk, nw = _per_dispatch(wpath, "WRITE_SIZE", kernel)
+    cf, _ = _per_dispatch(fpath, "FETCH_SIZE", copy_kernel)
+    cw, _ = _per_dispatch(wpath, "WRITE_SIZE", copy_kernel)
+    lines = ["# HBM traffic of the persistent alignment kernel, rocprofv3 --pmc (KiB per dispatch,",
+             "# median over dispatches), with a plain copy of copy_bytes bytes as the scale",
+             f"# command (FETCH_SIZE, then WRITE_SIZE in a second run): {command}",
+             f"kernel_source_hash = {kernel_source_hash()}",
+             f"kernel = {kernel}", f"dispatches = {min(nf, nw)}",
+             f"fetch_kb = {fk:.1f}", f"write_kb = {wk:.1f}",
+             f"copy_bytes = {copy_bytes}", f"copy_fetch_kb = {cf:.1f}", f"copy_write_kb = {cw:.1f}",
+             f"# scaled: read {fk * copy_bytes / cf / 1e9:.3f} GB, write {wk * copy_bytes / cw / 1e9:.3f} GB"
+             " per dispatch"]
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("dir")
+    a.add_argument("out")
+    a.add_argument("--command", required=True)
+    b = sub.add_parser("traffic")
+    b.add_argument("fetch_dir")
+    b.add_argument("write_dir")
+    b.add_argument("out")
+    b.add_argument("--copy-bytes", type=int, required=True)
+    b.add_argument("--command", required=True)
+    args = ap.parse_args(argv)
+    if args.cmd == "stats":
+        stats(args.dir, args.out, args.command)
+    else:
+        traffic(args.fetch_dir, args.write_dir, args.out, args.copy_bytes, args.command)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -135,7 +135,7 @@ def test_batched_order_invariant():
 
 
 def test_batched_with_large_trellises():
-    # S > 4096 runs on the 8-wave persistent kernel next to the 4-wave packs
+    # S > 4096 runs on the second (large-trellis) persistent kernel next to the packs
     rng = np.random.default_rng(41)
     utts = [synth.utterance(rng, 2 * L + 30, C, L, 0, 6.0, 1.0, None)
             for L, C in [(2100, 32), (3000, 256), (5000, 32), (8000, 256), (12000, 32), (16383, 32)]]
