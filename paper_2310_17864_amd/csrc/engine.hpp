@@ -431,86 +431,132 @@ __device__ __forceinline__ bool prologue_check(const Inst& in, int w, int lane) 
 // block.  Over one block the state drops by at most 62, so the block's codes
 // for the 63 states at and below the block's top state sit one per lane (the
 // "band"), each as two 32-frame words (moved, skipped) with frame i of the
-// block at bit 31-i; a frame then costs three readlanes.  The next block's
-// raw words are fetched before the chase for a 128-state window that covers
-// any exit state, and repacked and realigned (ds_bpermute) after it.
+// block at bit 31-i; a frame then costs two readlanes.  Lane i records the
+// state of the block's frame i; its label is fetched after the chase and
+// stored one block later.
+//
+// Fetches run two blocks ahead: at the top of block b (state e_b) the raw
+// words of block b-2 are requested for the 192 states below e_b (three
+// 64-state windows; the top of block b-2 is at most 124 below e_b).  After
+// block b-1's chase has fixed that top, the windows are realigned to it with
+// ds_bpermute and only the 64-state band is unpacked.  Every fetch is issued
+// unconditionally (clamped addresses; masking happens at unpack time, since
+// overwriting a register with a load in flight would wait for it), so the
+// compiler's vmcnt waits count exactly; the path stores go out through
+// inline assembly: the compiler does not see them, which keeps its waits for
+// loads exact instead of draining all memory operations (loads complete in
+// issue order among themselves whatever the stores do).
 
 struct Band {
   uint32_t mv, sk;
-  int lab;
 };
 
-// Raw backpointer words of one state for the 4 groups of a block.
-struct RawBand {
+// Raw backpointer words (moved-plane word, skipped-plane word) of one state
+// for the 4 groups of a block.
+struct RawWin {
   uint32_t wm[4], ws[4];
-  int lab;
-  int pm, ps;      // bit offset r of the moved / skipped plane in its word
-  int rm, rs;      // planes R in that word
 };
 
-__device__ __forceinline__ RawBand load_raw(const Inst& in, int blk, int ngrp, int top, int x0, int lane) {
-  RawBand r;
-#pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    r.wm[g] = 0u;
-    r.ws[g] = 0u;
-  }
-  r.lab = in.blank;
-  r.pm = r.ps = 0;
-  r.rm = r.rs = 1;
-  const int q = top - x0 - lane;
-  if (q < 0 || blk < 0) return r;
-  const int M = in.M, NQ = bp_words_per_lane(M);
+// Where state q's planes sit in a lane's words.
+struct PlaneLoc {
+  int wseg, ln;          // segment, lane
+  int qm, pm, rm;        // moved plane: word, bit offset, planes in the word
+  int qs, ps, rs;        // skipped plane (label slots; blank slots repeat the moved one)
+  bool odd;
+};
+
+__device__ __forceinline__ PlaneLoc plane_loc(int M, int q) {
+  PlaneLoc p;
   const int segsz = kWave * M;
-  const int wseg = q / segsz;
-  const int rr = q - wseg * segsz;
-  const int ln = rr / M;
-  const int j = rr - ln * M;
+  p.wseg = q / segsz;
+  const int rr = q - p.wseg * segsz;
+  p.ln = rr / M;
+  const int j = rr - p.ln * M;
+  p.odd = j % 2;
   const int pmv = plane_mv(M, j);
-  r.pm = pmv % 4;
-  r.rm = planes_in_word(M, pmv / 4);
-  const uint32_t* base = in.bp + ((int64_t)wseg * ngrp) * NQ * kWave + ln;
-  const bool odd = j % 2;
-  int psk = 0;
-  if (odd) {
-    psk = plane_sk(M, j);
-    r.ps = psk % 4;
-    r.rs = planes_in_word(M, psk / 4);
-    r.lab = in.lab[(q - 1) / 2];
-  }
+  const int psk = p.odd ? plane_sk(M, j) : pmv;
+  p.qm = pmv / 4;
+  p.pm = pmv % 4;
+  p.rm = planes_in_word(M, p.qm);
+  p.qs = psk / 4;
+  p.ps = psk % 4;
+  p.rs = planes_in_word(M, p.qs);
+  return p;
+}
+
+__device__ __forceinline__ RawWin load_win(const Inst& in, int blk, int ngrp, int q) {
+  RawWin r;
+  const int M = in.M, NQ = bp_words_per_lane(M);
+  const PlaneLoc p = plane_loc(M, q > 0 ? q : 0);
+  const uint32_t* base = in.bp + ((int64_t)p.wseg * ngrp) * NQ * kWave + p.ln;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
-    const int gi = 4 * blk + g;
-    if (gi < ngrp) {
-      const uint32_t* gb = base + (int64_t)gi * NQ * kWave;
-      r.wm[g] = gb[(pmv / 4) * kWave];
-      if (odd) r.ws[g] = gb[(psk / 4) * kWave];
-    }
+    int gi = 4 * blk + g;
+    gi = gi < ngrp ? gi : ngrp - 1;               // past the last group: unused bits
+    const uint32_t* gb = base + (int64_t)gi * NQ * kWave;
+    r.wm[g] = gb[p.qm * kWave];
+    r.ws[g] = gb[p.qs * kWave];
   }
   return r;
 }
 
-// The 8 frame bits of plane offset p (R planes per word) of word w, as the
-// top byte of the result in frame order (frame i at bit 31-i).
-__device__ __forceinline__ uint32_t group_bits(uint32_t w, int R, int p) {
-  uint32_t o = 0;
-#pragma unroll
-  for (int i = 0; i < kUnroll; ++i) o |= ((w >> (31 - R * i - p)) & 1u) << (31 - i);
-  return o;
-}
-
-__device__ __forceinline__ Band repack(const RawBand& r) {
-  Band b{0u, 0u, r.lab};
-#pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    b.mv |= group_bits(r.wm[g], r.rm, r.pm) >> (kUnroll * g);
-    b.sk |= group_bits(r.ws[g], r.rs, r.ps) >> (kUnroll * g);
-  }
-  return b;
+// The 8 frame bits of plane offset p in a word of R interleaved planes
+// (frame i at bit 31-(R*i+p)), moved to the top byte in frame order (frame i
+// at bit 31-i): mask, then merge neighbours in three doubling steps.
+__device__ __forceinline__ uint32_t gather8(uint32_t w, int R, int p) {
+  const uint32_t m0 = R == 4 ? 0x88888888u : R == 3 ? 0x92492400u : R == 2 ? 0xAAAA0000u : 0xFF000000u;
+  const uint32_t m1 = R == 4 ? 0xC0C0C0C0u : R == 3 ? 0xC30C3000u : R == 2 ? 0xCCCC0000u : 0xFF000000u;
+  const uint32_t m2 = R == 4 ? 0xF000F000u : R == 3 ? 0xF00F0000u : R == 2 ? 0xF0F00000u : 0xFF000000u;
+  uint32_t x = (w << p) & m0;
+  x = (x | (x << (R - 1))) & m1;
+  x = (x | (x << (2 * R - 2))) & m2;
+  x = (x | (x << (4 * R - 4))) & 0xFF000000u;
+  return x;
 }
 
 __device__ __forceinline__ uint32_t bperm(uint32_t v, int src_lane) {
   return (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane * 4, (int)v);
+}
+
+// Band of state q (= the windows' top - d - lane) from three windows: realign
+// with ds_bpermute and unpack, group by group.
+__device__ __forceinline__ Band band_of(const Inst& in, const RawWin& a, const RawWin& b, const RawWin& c,
+                                        int d, int q, int lane) {
+  const int x = d + lane;            // 0..191
+  const int k = x >> 6, src = x & (kWave - 1);
+  auto pick = [&](uint32_t va, uint32_t vb, uint32_t vc) __attribute__((always_inline)) {
+    const uint32_t ra = bperm(va, src), rb = bperm(vb, src), rc = bperm(vc, src);
+    return k == 0 ? ra : (k == 1 ? rb : rc);
+  };
+  const PlaneLoc p = plane_loc(in.M, q > 0 ? q : 0);
+  Band out{0u, 0u};
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    out.mv |= gather8(pick(a.wm[g], b.wm[g], c.wm[g]), p.rm, p.pm) >> (kUnroll * g);
+    out.sk |= gather8(pick(a.ws[g], b.ws[g], c.ws[g]), p.rs, p.ps) >> (kUnroll * g);
+  }
+  if (q < 0) out.mv = 0u;
+  if (q < 0 || !p.odd) out.sk = 0u;
+  return out;
+}
+
+// Band of state q straight from one window (no realignment).
+__device__ __forceinline__ Band band_direct(const Inst& in, const RawWin& a, int q) {
+  const PlaneLoc p = plane_loc(in.M, q > 0 ? q : 0);
+  Band out{0u, 0u};
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    out.mv |= gather8(a.wm[g], p.rm, p.pm) >> (kUnroll * g);
+    out.sk |= gather8(a.ws[g], p.rs, p.ps) >> (kUnroll * g);
+  }
+  if (q < 0) out.mv = 0u;
+  if (q < 0 || !p.odd) out.sk = 0u;
+  return out;
+}
+
+// Stores the compiler does not track (see above).
+__device__ __forceinline__ void store_untracked(void* p, uint32_t v) {
+  asm volatile("global_store_dword %0, %1, off" ::"v"(p), "v"(v) : "memory");
 }
 
 __device__ __forceinline__ void fill_outputs(const Inst& in, int lane, int path_val, float score_val) {
@@ -527,6 +573,8 @@ __device__ __forceinline__ void backtrack(const Inst& in, const FwdOut& fo, int 
   float total = fo.total;
   if (status == kOk && !fo.ok) status = kEdevice;
   if (status == kOk && total == neg_inf()) status = kEinfeasible;
+  // start with no memory operation in flight (see the loop head below)
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
 
   if (status != kOk) {
     const float fillv = (status == kEinfeasible) ? neg_inf() : __builtin_nanf("");
@@ -535,63 +583,98 @@ __device__ __forceinline__ void backtrack(const Inst& in, const FwdOut& fo, int 
   } else {
     const int nblk = (T - 1 + kBlk - 1) / kBlk;
     const int ngrp = (int)bp_groups(T);
-    int s = fo.send;
-    Band cur = repack(load_raw(in, nblk - 1, ngrp, s, 0, lane));
-    int pend_lab = 0;
-    float pend_sc = 0.f;
+    // with no labels every state is blank: the label reads hit path[0]
+    const int* labp = in.lab ? in.lab : in.path;
+    int e = fo.send;                       // state at the top of the current block
+    Band cur{0u, 0u};
+    // Two window sets alternate between "fetched for the block after next"
+    // and "being realigned for the next block"; the loop is unrolled by two so
+    // that no set is ever copied (a copy would wait for its loads).
+    RawWin setA[3], setB[3];
+    int ntop = e;                          // top the next block's windows were fetched below
+    if (nblk > 0) {
+      cur = band_direct(in, load_win(in, nblk - 1, ngrp, e - lane), e - lane);
+      const int nb = nblk - 2 >= 0 ? nblk - 2 : 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) setA[k] = load_win(in, nb, ngrp, e - k * kWave - lane);
+      // enter the loop with no load in flight: the compiler's waits at the
+      // loop head then only see the loop's own (exactly counted) fetches
+      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    }
+    int pend_lab = 0, pend_odd = 0;
     int pend_t0 = -1;
     int pend_n = 0;
-    for (int b = nblk - 1; b >= 0; --b) {
+    // One block: fetch block b-2's windows into `fetch`, chase block b, store
+    // the previous block's path, fetch this block's labels, then build block
+    // b-1's band from `next`.
+    auto step = [&](int b, RawWin (&next)[3], RawWin (&fetch)[3]) __attribute__((always_inline)) {
       const int n = (T - 1 - 32 * b) < kBlk ? (T - 1 - 32 * b) : kBlk;
-      const int top = s;
-      RawBand wa, wb;
-      if (b > 0) {
-        wa = load_raw(in, b - 1, ngrp, top, 0, lane);
-        wb = load_raw(in, b - 1, ngrp, top, kWave, lane);
+      const int top = e;
+      const int fb = b - 2 >= 0 ? b - 2 : 0;   // for b < 2 the fetch is unused
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        fetch[k] = load_win(in, fb, ngrp, top - k * kWave - lane);
+        __builtin_amdgcn_sched_barrier(0);     // bounds live address registers
       }
       // chase frames t = 32b+n .. 32b+1 (bit 31-i of the block's words)
-      int outlab = blank;
+      int outst = 0;
       for (int i = n - 1; i >= 0; --i) {
-        const int l = top - s;
-        const int lab = __builtin_amdgcn_readlane(cur.lab, l);
-        outlab = (lane == i) ? lab : outlab;
+        const int l = top - e;
+        outst = (lane == i) ? e : outst;
         const uint32_t m1 = (uint32_t)__builtin_amdgcn_readlane((int)cur.mv, l);
         const uint32_t m2 = (uint32_t)__builtin_amdgcn_readlane((int)cur.sk, l);
         const int bit = 31 - i;
         const int k = ((m2 >> bit) & 1u) ? 2 : (int)((m1 >> bit) & 1u);
-        s -= k;
+        e -= k;
       }
-      // outputs of the previous block (its score gathers have had a block's time)
-      if (pend_t0 >= 0 && lane < pend_n) {
-        in.path[pend_t0 + lane] = pend_lab;
-        in.scores[pend_t0 + lane] = pend_sc;
-      }
+      // path of the previous block (its label reads have had a block's time)
+      if (pend_t0 >= 0 && lane < pend_n)
+        store_untracked(in.path + pend_t0 + lane, (uint32_t)(pend_odd ? pend_lab : blank));
       pend_t0 = 32 * b + 1;
       pend_n = n;
-      pend_lab = outlab;
-      pend_sc = lane < n ? em[(int64_t)(pend_t0 + lane) * RS + outlab] : 0.f;
+      pend_odd = outst % 2;
+      pend_lab = labp[pend_odd ? (outst - 1) / 2 : 0];
       if (b > 0) {
-        const Band ba = repack(wa), bb = repack(wb);
-        const int d = top - s;   // 0..64: exit state = top - d
-        const int src = (lane + d) & (kWave - 1);
-        const bool hi = lane + d >= kWave;
-        const uint32_t amv = bperm(ba.mv, src), bmv = bperm(bb.mv, src);
-        const uint32_t ask = bperm(ba.sk, src), bsk = bperm(bb.sk, src);
-        const int alab = (int)bperm((uint32_t)ba.lab, src), blab = (int)bperm((uint32_t)bb.lab, src);
-        cur.mv = hi ? bmv : amv;
-        cur.sk = hi ? bsk : ask;
-        cur.lab = hi ? blab : alab;
+        cur = band_of(in, next[0], next[1], next[2], ntop - e, e - lane, lane);
+        ntop = top;
       }
+    };
+    // both steps unconditional inside the loop (a path around the second one
+    // would leave set B in flight at the loop head and force a full wait there)
+    int b = nblk - 1;
+    for (; b >= 1; b -= 2) {
+      step(b, setA, setB);
+      step(b - 1, setB, setA);
     }
-    if (pend_t0 >= 0 && lane < pend_n) {
-      in.path[pend_t0 + lane] = pend_lab;
-      in.scores[pend_t0 + lane] = pend_sc;
-    }
+    if (b == 0) step(0, setA, setB);
+    if (pend_t0 >= 0 && lane < pend_n)
+      store_untracked(in.path + pend_t0 + lane, (uint32_t)(pend_odd ? pend_lab : blank));
     // frame 0
     if (lane == 0) {
-      const int lab0 = (s % 2 == 0) ? blank : in.lab[(s - 1) / 2];
-      in.path[0] = lab0;
-      in.scores[0] = em[lab0];
+      const int lab0 = (e % 2 == 0) ? blank : in.lab[(e - 1) / 2];
+      store_untracked(in.path, (uint32_t)lab0);
+    }
+    // per-frame scores: emission[t, path[t]], four independent gathers per
+    // lane in flight (the path stores above are complete after the wait)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    for (int t0 = 0; t0 < T; t0 += 4 * kWave) {
+      int c[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int t = t0 + r * kWave + lane;
+        c[r] = t < T ? in.path[t] : -1;
+      }
+      float v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int t = t0 + r * kWave + lane;
+        v[r] = c[r] >= 0 ? em[(int64_t)t * RS + c[r]] : 0.f;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int t = t0 + r * kWave + lane;
+        if (c[r] >= 0) in.scores[t] = v[r];
+      }
     }
   }
   if (lane == 0) {
