@@ -111,8 +111,11 @@ struct SkipRep {
 
 template <int M>
 __device__ __forceinline__ void dp_frame(float (&a)[M], uint32_t (&acc)[bp_words_per_lane(M)],
-                                         const typename SkipRep<M>::T (&skip)[M / 2], float nb,
-                                         float eb, const float (&e)[M / 2]) {
+                                         const typename SkipRep<M>::T (&skip)[M / 2], float nbs,
+                                         float nb_in, float eb, const float (&e)[M / 2]) {
+  // lane 0 takes the boundary value from below; selected only where the two
+  // lowest states use it, so its LDS read may still be in flight until then
+  const float nb = sel(1ull, nb_in, nbs);
 #pragma unroll
   for (int j = M - 1; j >= 0; --j) {
     const float p1 = (j >= 1) ? a[j - 1] : nb;
@@ -275,12 +278,24 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   uint32_t* bpw = in.bp + (int64_t)w * ngrp * NQ * kWave + lane;
 
   const int hs = in.stride;
+  // Small lanes read each frame's emissions one frame ahead (M/2+1 more
+  // registers), hiding the LDS latency behind the previous frame's work.
+  constexpr bool kAhead = M <= 16;
+  float eb_c = 0.f, e_c[M / 2];
+#pragma unroll
+  for (int jj = 0; jj < M / 2; ++jj) e_c[jj] = 0.f;
   if (nsteps > 0) {
     dma_chunk(em, T, hs, 0, lane, ring_quarter(ring, 0));
     dma_chunk(em, T, hs, 1, lane, ring_quarter(ring, 1));
     dma_chunk(em, T, hs, 2, lane, ring_quarter(ring, 2));
     wait_vm_keep<kDmaAfter>();     // chunk 0 has landed
     dma_chunk(em, T, hs, 3, lane, ring_quarter(ring, 3));
+    if constexpr (kAhead) {
+      const float* r0 = ring_quarter(ring, 0);
+      eb_c = r0[blank];
+#pragma unroll
+      for (int jj = 0; jj < M / 2; ++jj) e_c[jj] = r0[eoff[jj]];
+    }
   }
 
   uint32_t acc[NQ];
@@ -292,9 +307,12 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   for (int b = 0; b < nblk && alive; ++b) {
     const int n = (nsteps - 32 * b) < kBlk ? (nsteps - 32 * b) : kBlk;
     // cross-segment flow control, once per 32-frame block
-    if (has_prev) alive &= wait_geq(&prev->prod, 32 * b + n);
+    // (one value past the block: the last frame reads the next one ahead; the
+    // producer publishes whole blocks, so this waits for the same event)
+    if (has_prev) alive &= wait_geq(&prev->prod, 32 * b + n + 1);
     if (has_next && 32 * b + n - kBnd + 1 > 0) alive &= wait_geq(&next->cons, 32 * b + n - kBnd + 1);
     if (!alive) break;
+    float bv_c = pv->bnd[(32 * b) % kBnd];   // boundary value of the block's first frame
 
 #pragma unroll 1
     for (int g = 0; g < kBlk / kUnroll; ++g) {
@@ -305,24 +323,41 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
       auto frame = [&](auto ic) __attribute__((always_inline)) {
         constexpr int i = decltype(ic)::value;
         const int uu = ubase + i;                // computes frame t = uu + 1
-        const float* rc = ring_quarter(ring, (i / 2) % 4) + (i % 2) * kMaxC;
-        const float eb = rc[blank];
-        float e[M / 2];
+        if constexpr (!kAhead) {
+          const float* rc = ring_quarter(ring, (i / 2) % 4) + (i % 2) * kMaxC;
+          eb_c = rc[blank];
 #pragma unroll
-        for (int jj = 0; jj < M / 2; ++jj) e[jj] = rc[eoff[jj]];
-        const float bv = pv->bnd[uu % kBnd];
-        const float nb_in = has_prev ? bv : neg_inf();
-        const float nb = shr1(a[M - 1], nb_in);
-        dp_frame<M>(a, acc, skip, nb, eb, e);
-        if (has_next && lane == kWave - 1) me->bnd[(uu + 1) % kBnd] = a[M - 1];
+          for (int jj = 0; jj < M / 2; ++jj) e_c[jj] = rc[eoff[jj]];
+        }
         if constexpr (i % 2 == 1) {
-          // a2: chunk k-1 is consumed; wait for chunk k (the next frame's)
-          // and refill chunk k-1's quarter with chunk k+3 once its reads
-          // have completed
+          // a2: wait for chunk k (the next frame's) and refill chunk k-1's
+          // quarter with chunk k+3 once its reads have completed (with
+          // read-ahead, this frame's values were read during the last one)
           const int k = (uu + 1) / 2;
           wait_vm_keep<kDmaAfter>();
           asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
           dma_chunk(em, T, hs, k + 3, lane, ring_quarter(ring, (i / 2) % 4));
+        }
+        // this frame's boundary value was read one frame ahead; read the
+        // next one first (LDS reads complete in order)
+        const float bv = bv_c;
+        bv_c = pv->bnd[(uu + 1) % kBnd];
+        float eb_n = 0.f, e_n[M / 2];
+        if constexpr (kAhead) {
+          // the next frame's values, read while this frame computes
+          const float* rn = ring_quarter(ring, ((i + 1) / 2) % 4) + ((i + 1) % 2) * kMaxC;
+          eb_n = rn[blank];
+#pragma unroll
+          for (int jj = 0; jj < M / 2; ++jj) e_n[jj] = rn[eoff[jj]];
+        }
+        const float nb_in = has_prev ? bv : neg_inf();
+        const float nbs = shr1(a[M - 1], a[M - 1]);
+        dp_frame<M>(a, acc, skip, nbs, nb_in, eb_c, e_c);
+        if (has_next && lane == kWave - 1) me->bnd[(uu + 1) % kBnd] = a[M - 1];
+        if constexpr (kAhead) {
+          eb_c = eb_n;
+#pragma unroll
+          for (int jj = 0; jj < M / 2; ++jj) e_c[jj] = e_n[jj];
         }
         u = uu;
         // keep each frame's instructions together: bounds live registers
@@ -355,8 +390,8 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
           for (int jj = 0; jj < M / 2; ++jj) e[jj] = rc[eoff[jj]];
           const float bv = pv->bnd[uu % kBnd];
           const float nb_in = has_prev ? bv : neg_inf();
-          const float nb = shr1(a[M - 1], nb_in);
-          dp_frame<M>(a, acc, skip, nb, eb, e);
+          const float nbs = shr1(a[M - 1], a[M - 1]);
+          dp_frame<M>(a, acc, skip, nbs, nb_in, eb, e);
           if (has_next && lane == kWave - 1) me->bnd[(uu + 1) % kBnd] = a[M - 1];
           u = uu;
         }
