@@ -63,15 +63,20 @@ int launch_single(ctcalign_ctx* ctx, const float* emission, int32_t T, int32_t C
   geometry_one(ctx, in);
   if (!geometry_supported_one(in.W, in.M) || !geo_ok(2 * L + 1, in.W, in.M)) return CTCALIGN_EINVAL;
 
-  const size_t need = round_up((size_t)bp_words(T, in.W, in.M) * 4, 256);
+  const size_t bp_need = round_up((size_t)bp_words(T, in.W, in.M) * 4, 256);
+  const bool multi = geometry_is_multi(in.W, in.M);
+  const size_t need = bp_need + (multi ? round_up(sizeof(XSync), 256) : 0);
+  char* ws;
   if (workspace) {
     if (ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255u)) return CTCALIGN_EINVAL;
-    in.bp = static_cast<uint32_t*>(workspace);
+    ws = static_cast<char*>(workspace);
   } else {
     rc = ctx->ws.reserve(need);
     if (rc) return rc;
-    in.bp = static_cast<uint32_t*>(ctx->ws.ptr);
+    ws = static_cast<char*>(ctx->ws.ptr);
   }
+  in.bp = reinterpret_cast<uint32_t*>(ws);
+  XSync* xs = multi ? reinterpret_cast<XSync*>(ws + bp_need) : nullptr;
 
   if (C == in.stride && aligned16(emission)) {
     in.em = emission;
@@ -84,7 +89,7 @@ int launch_single(ctcalign_ctx* ctx, const float* emission, int32_t T, int32_t C
     in.em = static_cast<float*>(ctx->pad.ptr);
   }
   CTCA_LOG(2, "align T=%d C=%d L=%d -> W=%d M=%d stride=%d", T, C, L, in.W, in.M, in.stride);
-  HIP_TRY(launch_one(in, st));
+  HIP_TRY(multi ? launch_multi(in, xs, st) : launch_one(in, st));
   return CTCALIGN_OK;
 }
 
@@ -236,7 +241,8 @@ int ctcalign_ctx_destroy(ctcalign_ctx* c) {
 size_t ctcalign_workspace_bytes(ctcalign_ctx* ctx, int32_t T, int32_t L, int32_t C) {
   if (!ctx || T < 1 || L < 0 || C < 1 || C > kMaxC || 2 * (int64_t)L + 1 > kMaxS) return 0;
   const Geo g = ctx->tune.pick_one(2 * L + 1, C);
-  return round_up((size_t)bp_words(T, g.W, g.M) * 4, 256);
+  return round_up((size_t)bp_words(T, g.W, g.M) * 4, 256) +
+         (geometry_is_multi(g.W, g.M) ? round_up(sizeof(XSync), 256) : 0);
 }
 
 int ctcalign_align_ex(ctcalign_ctx* ctx, const float* emission, int32_t T, int32_t C,
@@ -336,7 +342,7 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
     in.stride = row_stride_for(C[i]);
     const int S = 2 * L[i] + 1;
     const bool big = S > ctx->tune.max_pack_states();
-    const Geo g = big ? ctx->tune.pick_one(S, C[i]) : ctx->tune.pick_pack(S, C[i], T[i]);
+    const Geo g = big ? ctx->tune.pick_long(S) : ctx->tune.pick_pack(S, C[i], T[i]);
     const bool supported = big ? geometry_supported_long_batch(g.W, g.M) : geometry_supported_pack(g.W, g.M);
     if (!supported || !geo_ok(S, g.W, g.M)) {
       delete p;

@@ -207,6 +207,68 @@ __device__ __forceinline__ void wait_vm_keep() {
   asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
+// ---- boundaries between workgroups (multi layout) ---------------------------
+//
+// A segment whose lower neighbour runs in another workgroup copies each
+// block's boundary values from the global ring into an LDS ring of its own
+// (`in_lds`), after which the frame loop reads them exactly as from an LDS
+// neighbour; a segment whose upper neighbour runs in another workgroup
+// publishes each finished block from its own LDS ring to the global one.
+struct XLink {
+  XChan* in_ch = nullptr;    // ring from the lower neighbour's workgroup
+  XChan* out_ch = nullptr;   // ring to the upper neighbour's workgroup
+  SegSync* in_lds = nullptr; // local copy of the incoming values
+  int wl = 0;                // wave index in the workgroup
+};
+
+// Polls of global memory take a round trip each: a smaller bound (~seconds).
+constexpr int kXSpinLimit = 1 << 20;
+
+__device__ __forceinline__ uint64_t x_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void x_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Copies boundary values i0 .. i0+cnt-1 (cnt <= 64) from the global ring to
+// dst, waiting (bounded) until every slot holds its index.  Then tells the
+// producer how far it got.
+__device__ __forceinline__ bool x_pull(XChan* ch, SegSync* dst, int i0, int cnt, int lane) {
+  const int i = i0 + lane;
+  for (int it = 0; it < kXSpinLimit; ++it) {
+    uint64_t v = 0;
+    if (lane < cnt) v = x_load(&ch->slot[i % kXRing]);
+    const bool ok = lane >= cnt || (int32_t)(v >> 32) == i;
+    if (__builtin_amdgcn_ballot_w64(!ok) == 0) {
+      if (lane < cnt) dst->bnd[i % kBnd] = __builtin_bit_cast(float, (uint32_t)v);
+      if (lane == 0) __hip_atomic_store(&ch->cons, i0 + cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return true;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return false;
+}
+
+// Waits (bounded) until the consumer has taken every value that slot reuse
+// up to index i_end (exclusive) would overwrite.  `seen` caches its progress.
+__device__ __forceinline__ bool x_room(XChan* ch, int i_end, int& seen) {
+  for (int it = 0; it < kXSpinLimit && i_end - kXRing > seen; ++it) {
+    seen = __hip_atomic_load(&ch->cons, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (i_end - kXRing > seen) __builtin_amdgcn_s_sleep(2);
+  }
+  return i_end - kXRing <= seen;
+}
+
+// Publishes boundary values i0 .. i0+cnt-1 (cnt <= 64) of src to the ring.
+__device__ __forceinline__ void x_push(XChan* ch, const SegSync* src, int i0, int cnt, int lane) {
+  if (lane < cnt) {
+    const int i = i0 + lane;
+    const uint32_t bits = __builtin_bit_cast(uint32_t, src->bnd[i % kBnd]);
+    x_store(&ch->slot[i % kXRing], ((uint64_t)(uint32_t)i << 32) | bits);
+  }
+}
+
 // Where segment outcomes go for the backtrack.
 struct FwdOut {
   float total;
@@ -218,9 +280,12 @@ struct FwdOut {
 //
 // `sy` points at the SegSync of segment 0 of this instance; the caller has
 // cleared it and passed a workgroup barrier after `prologue_check`.
-template <int M>
+// kX: multi layout; `sy` is then this workgroup's SegSync array and xl says
+// which neighbours sit in other workgroups.
+template <int M, bool kX = false>
 __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, const int lane,
-                                                  const Ring& ring, SegSync* sy, bool labels_bad) {
+                                                  const Ring& ring, SegSync* sy, bool labels_bad,
+                                                  const XLink& xl = XLink{}) {
   const int T = in.T, L = in.L, blank = in.blank, W = in.W;
   const int S = 2 * L + 1;                  // state counts fit int32 (host-checked)
   const int sbase = (w * kWave + lane) * M;
@@ -260,15 +325,23 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   }
 
   const bool has_next = w + 1 < W, has_prev = w > 0;
-  SegSync* me = sy + w;
-  SegSync* prev = has_prev ? sy + w - 1 : nullptr;
-  SegSync* next = has_next ? sy + w + 1 : nullptr;
+  const int wl = kX ? xl.wl : w;          // index into sy
+  // neighbours in other workgroups (multi layout only)
+  const bool prev_x = kX && has_prev && xl.in_ch != nullptr;
+  const bool next_x = kX && has_next && xl.out_ch != nullptr;
+  SegSync* me = sy + wl;
+  SegSync* prev = has_prev ? (prev_x ? xl.in_lds : sy + wl - 1) : nullptr;
+  SegSync* next = (has_next && !next_x) ? sy + wl + 1 : nullptr;
   // boundary values are read every frame through a pointer that always points
   // into the SegSync array (the compiler then knows it cannot alias the ring)
-  const SegSync* pv = sy + (has_prev ? w - 1 : w);
+  const SegSync* pv = has_prev ? prev : me;
+  int x_seen = 0;                         // consumer progress seen by a cross-workgroup producer
   if (has_next) {
     if (lane == kWave - 1) me->bnd[0] = a[M - 1];
-    lds_store_rel(&me->prod, 1);
+    if (next_x)
+      x_push(xl.out_ch, me, 0, 1, lane);
+    else
+      lds_store_rel(&me->prod, 1);
   }
 
   const int nsteps = T - 1;               // frames 1..T-1
@@ -309,8 +382,16 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
     // cross-segment flow control, once per 32-frame block
     // (one value past the block: the last frame reads the next one ahead; the
     // producer publishes whole blocks, so this waits for the same event)
-    if (has_prev) alive &= wait_geq(&prev->prod, 32 * b + n + 1);
-    if (has_next && 32 * b + n - kBnd + 1 > 0) alive &= wait_geq(&next->cons, 32 * b + n - kBnd + 1);
+    if (has_prev) {
+      if (prev_x)
+        alive &= x_pull(xl.in_ch, prev, 32 * b, n + 1, lane);   // values 32b .. 32b+n
+      else
+        alive &= wait_geq(&prev->prod, 32 * b + n + 1);
+    }
+    if (next_x)
+      alive &= x_room(xl.out_ch, 32 * b + n + 1, x_seen);
+    else if (has_next && 32 * b + n - kBnd + 1 > 0)
+      alive &= wait_geq(&next->cons, 32 * b + n - kBnd + 1);
     if (!alive) break;
     float bv_c = pv->bnd[(32 * b) % kBnd];   // boundary value of the block's first frame
 
@@ -408,8 +489,13 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
       }
     }
 
-    if (has_next) lds_store_rel(&me->prod, 32 * b + n + 1);
-    if (has_prev) lds_store_rel(&me->cons, 32 * b + n);
+    if (has_next) {
+      if (next_x)
+        x_push(xl.out_ch, me, 32 * b + 1, n, lane);             // values 32b+1 .. 32b+n
+      else
+        lds_store_rel(&me->prod, 32 * b + n + 1);
+    }
+    if (has_prev && !prev_x) lds_store_rel(&me->cons, 32 * b + n);
   }
   out.ok = alive ? 1 : 0;
   wait_dma();   // no copy into LDS may outlive this instance

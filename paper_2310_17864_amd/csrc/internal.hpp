@@ -32,6 +32,27 @@ struct Inst {
   int32_t prio;        // wave issue priority 0..3
 };
 
+// Long alignments spread over several workgroups ("multi" layout): segment w
+// runs on wave w % kXWaves of workgroup w / kXWaves.  Neighbouring segments in
+// different workgroups exchange boundary values through a ring of 64-bit
+// slots in global memory, each holding (value bits, frame index) so that a
+// reader recognises a slot written for the index it wants; all accesses are
+// agent-scope relaxed atomics.  The region sits after the backpointers in
+// the workspace and is reset (every word -1) before each launch.
+constexpr int kXWaves = 8;        // waves per workgroup
+constexpr int kXMaxGroups = 8;    // workgroups per alignment
+constexpr int kXRing = 512;       // slots per cross-workgroup boundary
+struct XChan {
+  uint64_t slot[kXRing];
+  int32_t cons;                   // frames the consumer has taken (next index it needs)
+  int32_t pad[31];
+};
+struct XSync {
+  XChan ch[kXMaxGroups - 1];      // ch[g]: from workgroup g to workgroup g+1
+  int32_t done[kXWaves * kXMaxGroups];   // 1 once segment w's backpointers are visible
+};
+__host__ __device__ constexpr bool geometry_is_multi(int W, int M) { return M <= 16 && W > 4; }
+
 // A workgroup-sized work item of the persistent kernel: wave k runs segment
 // seg[k] of instance inst[k] (inst < 0: idle); the W segments of an instance
 // sit on consecutive waves starting at first[k].

@@ -179,6 +179,69 @@ __global__ void __launch_bounds__(512) k_persistent_long(const Inst* __restrict_
 
 #undef CTCA_CASE
 
+// ---- multi layout: one long alignment over several workgroups ---------------
+
+__device__ __forceinline__ bool wait_geq_agent(int* p, int need) {
+  for (int n = 0; n < kXSpinLimit; ++n) {
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return true;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return false;
+}
+
+template <int M>
+__device__ __forceinline__ void run_multi(const Inst& in, XSync* xs, SegSync* sy, const Ring& ring,
+                                          int g, int wl, int lane, bool bad) {
+  const int w = g * kXWaves + wl;
+  if (w >= in.W) return;
+  XLink xl;
+  xl.wl = wl;
+  xl.in_lds = sy + kXWaves;
+  if (wl == 0 && g > 0) xl.in_ch = &xs->ch[g - 1];
+  if (wl == kXWaves - 1 && w + 1 < in.W) xl.out_ch = &xs->ch[g];
+  const FwdOut fo = segment_forward<M, true>(in, w, lane, ring, sy, bad, xl);
+  if (w + 1 < in.W) {
+    // backpointers visible device-wide, then the flag
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) __hip_atomic_store(&xs->done[w], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    bool ok = fo.ok != 0;
+    for (int k = 0; k + 1 < in.W; ++k) ok &= wait_geq_agent(&xs->done[k], 1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    FwdOut f2 = fo;
+    f2.ok = ok ? 1 : 0;
+    backtrack(in, f2, bad ? kEinval : kOk, lane);
+  }
+}
+
+// Workgroup g runs segments 8g .. 8g+7 of one alignment; all workgroups are
+// resident together (one launch of at most kXMaxGroups workgroups).  Every
+// workgroup validates the whole transcript itself, so the verdict needs no
+// communication between workgroups.
+__global__ void __launch_bounds__(kWave * kXWaves) k_multi(Inst in, XSync* xs) {
+  __shared__ SegSync sy[kXWaves + 1];   // + the copy of the incoming boundary
+  __shared__ __attribute__((aligned(16))) float ring[kXWaves][kRing * kMaxC];
+  const int wl = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  reset_sync(sy + wl, lane);
+  if (wl == 0) reset_sync(sy + kXWaves, lane);
+  bool bad = false;
+  for (int i = threadIdx.x; i < in.L; i += blockDim.x) {
+    const int v = in.lab[i];
+    bad |= (v < 0) | (v >= in.C) | (v == in.blank);
+  }
+  bad = __syncthreads_or(bad);
+  const int g = blockIdx.x;
+  const Ring r{ring[wl]};
+  switch (in.M) {
+    case 8: run_multi<8>(in, xs, sy, r, g, wl, lane, bad); break;
+    case 10: run_multi<10>(in, xs, sy, r, g, wl, lane, bad); break;
+    case 12: run_multi<12>(in, xs, sy, r, g, wl, lane, bad); break;
+    case 14: run_multi<14>(in, xs, sy, r, g, wl, lane, bad); break;
+    case 16: run_multi<16>(in, xs, sy, r, g, wl, lane, bad); break;
+    default: break;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_pad(const PadDesc* __restrict__ d) {
   const PadDesc pd = d[blockIdx.y];
   const int64_t total = (int64_t)pd.T * pd.stride;
@@ -270,8 +333,11 @@ static const int kOneMenu[] = {2, 4, 6, 8, 10, 12, 14, 16};
 static const int kLongMenu[] = {16, 24, 32, 40, 48, 56, 60, 64};
 static const int kPackMenuK[] = {2, 4, 6, 8, 10, 12, 14, 16};
 
+static const int kMultiMenu[] = {8, 10, 12, 14, 16};
+
 bool geometry_supported_one(int W, int M) {
   if (W >= 1 && W <= 4 && m_in(M, kOneMenu, 8)) return true;
+  if (geometry_is_multi(W, M) && W <= kXWaves * kXMaxGroups && m_in(M, kMultiMenu, 5)) return true;
   if (W >= 1 && W <= 8 && m_in(M, kLongMenu, 8)) return true;
   return false;
 }
@@ -286,6 +352,16 @@ hipError_t launch_one(const Inst& in, hipStream_t st) {
     hipLaunchKernelGGL(k_one, dim3(1), block, 0, st, in);
   else
     hipLaunchKernelGGL(k_one_long, dim3(1), block, 0, st, in);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi(const Inst& in, XSync* xs, hipStream_t st) {
+  // every slot index and flag starts at -1 (a fill kernel: graph-capturable)
+  const int nwords = (int)(sizeof(XSync) / sizeof(int));
+  hipLaunchKernelGGL(k_fill, dim3((nwords + 255) / 256), dim3(256), 0, st, reinterpret_cast<int*>(xs),
+                     nwords, -1);
+  const int groups = (in.W + kXWaves - 1) / kXWaves;
+  hipLaunchKernelGGL(k_multi, dim3(groups), dim3(kWave * kXWaves), 0, st, in, xs);
   return hipGetLastError();
 }
 

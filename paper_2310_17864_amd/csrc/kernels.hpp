@@ -9,6 +9,8 @@ namespace ctca {
 bool geometry_supported_one(int W, int M);
 bool geometry_supported_pack(int W, int M);
 hipError_t launch_one(const Inst& in, hipStream_t st);
+// one long alignment over ceil(W/8) workgroups; xs: its sync region (reset here)
+hipError_t launch_multi(const Inst& in, XSync* xs, hipStream_t st);
 hipError_t launch_persistent(const Inst* d_insts, const Pack* d_packs, int npacks, int* d_head,
                              int grid, hipStream_t st, int64_t* d_trace = nullptr);
 hipError_t launch_fill(int* p, int n, int v, hipStream_t st);

@@ -397,7 +397,7 @@ int ctcalign_server_submit(ctcalign_server* s, const ctcalign_request* r, uint64
     p->g = s->ctx->tune.pick_pack(S, r->C, r->T);
     p->pack = true;
   } else {
-    p->g = s->ctx->tune.pick_one(S, r->C);
+    p->g = s->ctx->tune.pick_long(S);
     p->pack = false;
   }
   if (p->g.W == 0 || !geo_ok(S, p->g.W, p->g.M)) {
@@ -411,7 +411,7 @@ int ctcalign_server_submit(ctcalign_server* s, const ctcalign_request* r, uint64
   if (p->pad_bytes && p->pack) {
     // padded emissions go through a single launch (its pad kernel runs on the same stream)
     p->pack = false;
-    p->g = s->ctx->tune.pick_one(S, r->C);
+    p->g = s->ctx->tune.pick_long(S);
     p->bp_bytes = round_up((size_t)bp_words(r->T, p->g.W, p->g.M) * 4, 256);
   }
   SchedReq* q = new (std::nothrow) SchedReq();

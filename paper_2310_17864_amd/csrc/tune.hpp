@@ -19,6 +19,7 @@ struct Geo {
 constexpr int kMenuOne[] = {2, 4, 6, 8, 10, 12, 14, 16};          // k_one, W <= 4
 constexpr int kMenuLong[] = {16, 24, 32, 40, 48, 56, 60, 64};     // k_one_long, W <= 8
 constexpr int kMenuPack[] = {2, 4, 6, 8, 10, 12, 14, 16};         // k_persistent, W in {1,2,4}
+constexpr int kMenuMulti[] = {8, 10, 12, 14, 16};                          // k_multi, 4 < W <= 64
 
 // Geometry is usable iff it covers S and the top segment holds S-1 and S-2
 // (the end-state choice reads both from one wavefront's registers).
@@ -66,6 +67,17 @@ struct TuneTable {
         for (int M : kMenuOne)
           if (geo_ok(S, W, M)) return Geo{W, M};
     }
+    // larger: spread over several workgroups, few states per lane (the
+    // per-frame latency grows with M; more workgroups cost only pipeline fill)
+    for (int M : kMenuMulti) {
+      const int W = (S + kWave * M - 1) / (kWave * M);
+      if (W <= kXWaves * kXMaxGroups && geo_ok(S, W, M)) return Geo{W, M};
+    }
+    return pick_long(S);
+  }
+
+  // One workgroup of up to 8 waves (the batched large-trellis kernel).
+  Geo pick_long(int S) const {
     for (int M : kMenuLong)
       for (int W = 8; W >= 1; --W)
         if (geo_ok(S, W, M)) return Geo{W, M};

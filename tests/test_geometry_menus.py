@@ -32,3 +32,13 @@ def test_single_menus_cover_all_sizes():
             if not (any(geo_ok(S, W, M) for W in range(1, 5) for M in one)
                     or any(geo_ok(S, W, M) for W in range(1, 9) for M in long_))]
     assert gaps == []
+
+
+def test_multi_menu_covers_long_single_launches():
+    # single launches above 4096 states use the multi-workgroup layout: the
+    # chooser takes W = ceil(S / (64 M)) for the first M of the menu that
+    # holds S; every odd S (S = 2L + 1) up to 32768 must find one with W <= 64
+    multi = menu("kMenuMulti")
+    gaps = [S for S in range(4097, 32769, 2)
+            if not any(geo_ok(S, -(-S // (64 * M)), M) and -(-S // (64 * M)) <= 64 for M in multi)]
+    assert gaps == []

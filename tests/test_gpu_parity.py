@@ -161,3 +161,13 @@ def test_token_spans_match_oracle():
         assert np.array_equal(tok.cpu().numpy(), rt) and np.array_equal(tok.cpu().numpy(), u.labels)
         assert np.array_equal(st.cpu().numpy(), rs) and np.array_equal(en.cpu().numpy(), re)
         assert np.array_equal(sc.cpu().numpy().view(np.uint32), rsc.view(np.uint32))
+
+
+@pytest.mark.parametrize("L,T", [(2049, 4200), (2500, 5100), (4096, 8300), (7000, 14100), (9000, 18100),
+                                 (12288, 24700), (16383, 32800)])
+def test_multi_workgroup_layouts(L, T):
+    # S > 4096 spreads over ceil(W/8) workgroups (W = ceil(S/(64 M)), M = 8):
+    # cross-workgroup boundaries, a top workgroup of one to eight waves
+    r = np.random.default_rng(L)
+    u = synth.utterance(r, T, 32 if L % 2 else 256, L, 0, 6.0, 1.0, 0.1)
+    assert compare_one(u.emission, u.labels, 0, f"multiL{L}") == []
