@@ -568,9 +568,28 @@ __device__ __forceinline__ bool prologue_check(const Inst& in, int w, int lane) 
 // loads exact instead of draining all memory operations (loads complete in
 // issue order among themselves whatever the stores do).
 
+// A state's codes k for the 32 frames of a block, 2 bits per frame: frame i
+// of the block at bits 31-2i, 30-2i of c0 (i < 16) or 63-2i, 62-2i of c1.
 struct Band {
-  uint32_t mv, sk;
+  uint32_t c0, c1;
 };
+
+// bit j of the low 16 bits -> bit 2j
+__device__ __forceinline__ uint32_t spread16(uint32_t x) {
+  x &= 0xFFFFu;
+  x = (x | (x << 8)) & 0x00FF00FFu;
+  x = (x | (x << 4)) & 0x0F0F0F0Fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  x = (x | (x << 1)) & 0x55555555u;
+  return x;
+}
+
+// codes from the moved / skipped words (frame i at bit 31-i): k = 2 if
+// skipped, else the moved bit
+__device__ __forceinline__ Band make_band(uint32_t mv, uint32_t sk) {
+  const uint32_t lo = mv & ~sk;
+  return Band{(spread16(sk >> 16) << 1) | spread16(lo >> 16), (spread16(sk) << 1) | spread16(lo)};
+}
 
 // Raw backpointer words (moved-plane word, skipped-plane word) of one state
 // for the 4 groups of a block.
@@ -586,7 +605,8 @@ struct PlaneLoc {
   bool odd;
 };
 
-__device__ __forceinline__ PlaneLoc plane_loc(int M, int q) {
+template <int M>
+__device__ __forceinline__ PlaneLoc plane_loc(int q) {
   PlaneLoc p;
   const int segsz = kWave * M;
   p.wseg = q / segsz;
@@ -605,10 +625,11 @@ __device__ __forceinline__ PlaneLoc plane_loc(int M, int q) {
   return p;
 }
 
+template <int M>
 __device__ __forceinline__ RawWin load_win(const Inst& in, int blk, int ngrp, int q) {
   RawWin r;
-  const int M = in.M, NQ = bp_words_per_lane(M);
-  const PlaneLoc p = plane_loc(M, q > 0 ? q : 0);
+  constexpr int NQ = bp_words_per_lane(M);
+  const PlaneLoc p = plane_loc<M>(q > 0 ? q : 0);
   const uint32_t* base = in.bp + ((int64_t)p.wseg * ngrp) * NQ * kWave + p.ln;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
@@ -641,38 +662,49 @@ __device__ __forceinline__ uint32_t bperm(uint32_t v, int src_lane) {
 
 // Band of state q (= the windows' top - d - lane) from three windows: realign
 // with ds_bpermute and unpack, group by group.
-__device__ __forceinline__ Band band_of(const Inst& in, const RawWin& a, const RawWin& b, const RawWin& c,
-                                        int d, int q, int lane) {
+template <int M>
+__device__ __forceinline__ Band band_of(const RawWin& a, const RawWin& b, const RawWin& c, int d, int q,
+                                        int lane) {
   const int x = d + lane;            // 0..191
   const int k = x >> 6, src = x & (kWave - 1);
   auto pick = [&](uint32_t va, uint32_t vb, uint32_t vc) __attribute__((always_inline)) {
     const uint32_t ra = bperm(va, src), rb = bperm(vb, src), rc = bperm(vc, src);
     return k == 0 ? ra : (k == 1 ? rb : rc);
   };
-  const PlaneLoc p = plane_loc(in.M, q > 0 ? q : 0);
-  Band out{0u, 0u};
+  const PlaneLoc p = plane_loc<M>(q > 0 ? q : 0);
+  uint32_t mv = 0u, sk = 0u;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
-    out.mv |= gather8(pick(a.wm[g], b.wm[g], c.wm[g]), p.rm, p.pm) >> (kUnroll * g);
-    out.sk |= gather8(pick(a.ws[g], b.ws[g], c.ws[g]), p.rs, p.ps) >> (kUnroll * g);
+    mv |= gather8(pick(a.wm[g], b.wm[g], c.wm[g]), p.rm, p.pm) >> (kUnroll * g);
+    sk |= gather8(pick(a.ws[g], b.ws[g], c.ws[g]), p.rs, p.ps) >> (kUnroll * g);
   }
-  if (q < 0) out.mv = 0u;
-  if (q < 0 || !p.odd) out.sk = 0u;
-  return out;
+  if (q < 0) mv = 0u;
+  if (q < 0 || !p.odd) sk = 0u;
+  return make_band(mv, sk);
 }
 
 // Band of state q straight from one window (no realignment).
-__device__ __forceinline__ Band band_direct(const Inst& in, const RawWin& a, int q) {
-  const PlaneLoc p = plane_loc(in.M, q > 0 ? q : 0);
-  Band out{0u, 0u};
+template <int M>
+__device__ __forceinline__ Band band_direct(const RawWin& a, int q) {
+  const PlaneLoc p = plane_loc<M>(q > 0 ? q : 0);
+  uint32_t mv = 0u, sk = 0u;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
-    out.mv |= gather8(a.wm[g], p.rm, p.pm) >> (kUnroll * g);
-    out.sk |= gather8(a.ws[g], p.rs, p.ps) >> (kUnroll * g);
+    mv |= gather8(a.wm[g], p.rm, p.pm) >> (kUnroll * g);
+    sk |= gather8(a.ws[g], p.rs, p.ps) >> (kUnroll * g);
   }
-  if (q < 0) out.mv = 0u;
-  if (q < 0 || !p.odd) out.sk = 0u;
-  return out;
+  if (q < 0) mv = 0u;
+  if (q < 0 || !p.odd) sk = 0u;
+  return make_band(mv, sk);
+}
+
+// f(integral_constant<N-1>), ..., f(integral_constant<0>)
+template <int N, typename F>
+__device__ __forceinline__ void unroll_down(F&& f) {
+  if constexpr (N > 0) {
+    f(std::integral_constant<int, N - 1>{});
+    unroll_down<N - 1>(f);
+  }
 }
 
 // Stores the compiler does not track (see above).
@@ -687,6 +719,7 @@ __device__ __forceinline__ void fill_outputs(const Inst& in, int lane, int path_
   }
 }
 
+template <int M>
 __device__ __forceinline__ void backtrack(const Inst& in, const FwdOut& fo, int status_in, int lane) {
   const int T = in.T, RS = in.stride, blank = in.blank;   // RS: emission row stride
   const float* em = in.em;
@@ -714,10 +747,10 @@ __device__ __forceinline__ void backtrack(const Inst& in, const FwdOut& fo, int 
     RawWin setA[3], setB[3];
     int ntop = e;                          // top the next block's windows were fetched below
     if (nblk > 0) {
-      cur = band_direct(in, load_win(in, nblk - 1, ngrp, e - lane), e - lane);
+      cur = band_direct<M>(load_win<M>(in, nblk - 1, ngrp, e - lane), e - lane);
       const int nb = nblk - 2 >= 0 ? nblk - 2 : 0;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) setA[k] = load_win(in, nb, ngrp, e - k * kWave - lane);
+      for (int k = 0; k < 3; ++k) setA[k] = load_win<M>(in, nb, ngrp, e - k * kWave - lane);
       // enter the loop with no load in flight: the compiler's waits at the
       // loop head then only see the loop's own (exactly counted) fetches
       __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
@@ -734,19 +767,31 @@ __device__ __forceinline__ void backtrack(const Inst& in, const FwdOut& fo, int 
       const int fb = b - 2 >= 0 ? b - 2 : 0;   // for b < 2 the fetch is unused
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        fetch[k] = load_win(in, fb, ngrp, top - k * kWave - lane);
+        fetch[k] = load_win<M>(in, fb, ngrp, top - k * kWave - lane);
         __builtin_amdgcn_sched_barrier(0);     // bounds live address registers
       }
-      // chase frames t = 32b+n .. 32b+1 (bit 31-i of the block's words)
-      int outst = 0;
-      for (int i = n - 1; i >= 0; --i) {
+      // chase frames t = 32b+n .. 32b+1: one readlane of the state's code
+      // word per frame (fully unrolled for whole blocks)
+      int outst = 0;                       // lane i: the state at the block's frame i
+      auto step_code = [&](int i) __attribute__((always_inline)) {
         const int l = top - e;
-        outst = (lane == i) ? e : outst;
-        const uint32_t m1 = (uint32_t)__builtin_amdgcn_readlane((int)cur.mv, l);
-        const uint32_t m2 = (uint32_t)__builtin_amdgcn_readlane((int)cur.sk, l);
-        const int bit = 31 - i;
-        const int k = ((m2 >> bit) & 1u) ? 2 : (int)((m1 >> bit) & 1u);
-        e -= k;
+        const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)(i < 16 ? cur.c0 : cur.c1), l);
+        e -= (int)((w >> ((i < 16 ? 30 : 62) - 2 * i)) & 3u);
+      };
+      if (n == kBlk) {
+        // whole block: frame i's state goes to lane i by v_writelane with an
+        // immediate lane index (no per-frame lane mask)
+        auto chase_c = [&](auto ic) __attribute__((always_inline)) {
+          constexpr int i = decltype(ic)::value;
+          asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(outst) : "s"(__builtin_amdgcn_readfirstlane(e)), "n"(i));
+          step_code(i);
+        };
+        unroll_down<kBlk>(chase_c);
+      } else {
+        for (int i = n - 1; i >= 0; --i) {
+          outst = (lane == i) ? e : outst;
+          step_code(i);
+        }
       }
       // path of the previous block (its label reads have had a block's time)
       if (pend_t0 >= 0 && lane < pend_n)
@@ -756,7 +801,7 @@ __device__ __forceinline__ void backtrack(const Inst& in, const FwdOut& fo, int 
       pend_odd = outst % 2;
       pend_lab = labp[pend_odd ? (outst - 1) / 2 : 0];
       if (b > 0) {
-        cur = band_of(in, next[0], next[1], next[2], ntop - e, e - lane, lane);
+        cur = band_of<M>(next[0], next[1], next[2], ntop - e, e - lane, lane);
         ntop = top;
       }
     };

@@ -36,7 +36,7 @@ __device__ __forceinline__ void run_wave(const Inst& in, int w, int lane, SegSyn
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     FwdOut f2 = fo;
     f2.ok = ok ? 1 : 0;
-    backtrack(in, f2, any_bad ? kEinval : kOk, lane);
+    backtrack<M>(in, f2, any_bad ? kEinval : kOk, lane);
   }
 }
 
@@ -210,7 +210,7 @@ __device__ __forceinline__ void run_multi(const Inst& in, XSync* xs, SegSync* sy
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     FwdOut f2 = fo;
     f2.ok = ok ? 1 : 0;
-    backtrack(in, f2, bad ? kEinval : kOk, lane);
+    backtrack<M>(in, f2, bad ? kEinval : kOk, lane);
   }
 }
 
