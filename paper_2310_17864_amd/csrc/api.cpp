@@ -353,13 +353,42 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
     in.M = g.M;
     in.prio = 0;
     cost[i] = (double)T[i] * ctx->tune.step_cost(g, in.stride);
-    bp_off[i] = bp_total;
-    bp_total += round_up((size_t)bp_words(T[i], in.W, in.M) * 4, 256);
     const float* src = emissions + em_off[i];
     if (C[i] != in.stride || !aligned16(src)) {
       pad_off[i] = pad_total;
       pad_total += round_up((size_t)T[i] * in.stride * sizeof(float), 256);
     }
+  }
+
+  // The batch's longest chains bound the whole pass: the ones whose chain
+  // (frames x per-frame latency of their pack layout) is close to the longest
+  // run in 8-wave workgroups with fewer states per lane instead.
+  std::vector<char> is_crit(N, 0);
+  std::vector<int> crit_order;
+  {
+    std::vector<int> cand;
+    double top = 0;
+    for (int i = 0; i < N; ++i)
+      if (!is_long[i]) top = std::max(top, ctx->tune.chain_ns(insts[i]));
+    for (int i = 0; i < N; ++i)
+      if (!is_long[i] && top > 0 && ctx->tune.chain_ns(insts[i]) >= ctx->tune.crit_frac * top) cand.push_back(i);
+    std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) {
+      return ctx->tune.chain_ns(insts[a]) > ctx->tune.chain_ns(insts[b]);
+    });
+    if ((int)cand.size() > ctx->tune.crit_max()) cand.resize(ctx->tune.crit_max());
+    for (int i : cand) {
+      const Geo g = ctx->tune.pick_crit(2 * insts[i].L + 1);
+      if (g.W == 0 || !geometry_supported_crit(g.W, g.M) || g.M >= insts[i].M) continue;
+      insts[i].W = g.W;
+      insts[i].M = g.M;
+      insts[i].prio = 3;         // issue priority over the packs sharing its CU
+      is_crit[i] = 1;
+      crit_order.push_back(i);   // longest chain first
+    }
+  }
+  for (int i = 0; i < N; ++i) {
+    bp_off[i] = bp_total;
+    bp_total += round_up((size_t)bp_words(T[i], insts[i].W, insts[i].M) * 4, 256);
   }
 
   // LPT order: most expensive first
@@ -386,6 +415,7 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
   for (int W = 1; W <= kPackWaves; ++W) open[W] = blank_pack();
   std::vector<int> long_order;
   for (int idx : order) {
+    if (is_crit[idx]) continue;
     if (is_long[idx]) {
       long_order.push_back(idx);   // already longest first
       continue;
@@ -450,6 +480,12 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
   }
   p->npad = (int)pads.size();
   p->nlong = (int)long_order.size();
+  p->ncrit = (int)crit_order.size();
+  if (p->ncrit &&
+      ((rc = map_hip(hipMalloc((void**)&p->d_crit, sizeof(int) * (p->ncrit + 1)), "crit")) ||
+       (rc = map_hip(hipMemcpy(p->d_crit, crit_order.data(), sizeof(int) * p->ncrit,
+                               hipMemcpyHostToDevice), "h2d"))))
+    return fail(rc);
   if (p->nlong &&
       ((rc = map_hip(hipMalloc((void**)&p->d_order, sizeof(int) * p->nlong), "order")) ||
        (rc = map_hip(hipMemcpy(p->d_order, long_order.data(), sizeof(int) * p->nlong,
@@ -489,6 +525,16 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
     return fail(rc);
   hipError_t e = hipSuccess;
   if (p->npad) e = launch_pad(p->d_pad, p->npad, p->pad_max, p->cap_stream);
+  // the longest chains on a parallel branch, launched first
+  if (e == hipSuccess && p->ncrit) {
+    if ((e = hipStreamCreateWithFlags(&p->crit_stream, hipStreamNonBlocking)) == hipSuccess &&
+        (e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming)) == hipSuccess &&
+        (e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming)) == hipSuccess &&
+        (e = hipEventRecord(p->ev_fork, p->cap_stream)) == hipSuccess &&
+        (e = hipStreamWaitEvent(p->crit_stream, p->ev_fork, 0)) == hipSuccess &&
+        (e = launch_persistent_crit(p->d_insts, p->d_crit, p->ncrit, p->crit_stream)) == hipSuccess)
+      e = hipEventRecord(p->ev_join, p->crit_stream);
+  }
   if (e == hipSuccess) e = launch_fill(p->d_head, 1, 0, p->cap_stream);
   if (e == hipSuccess && p->npacks)
     e = launch_persistent(p->d_insts, p->d_packs, p->npacks, p->d_head, p->grid, p->cap_stream,
@@ -497,6 +543,7 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
   if (e == hipSuccess && p->nlong)
     e = launch_persistent_long(p->d_insts, p->d_order, p->nlong, p->d_head_long,
                                std::min(p->nlong, ctx->num_cu * 4), p->cap_stream);
+  if (e == hipSuccess && p->ncrit) e = hipStreamWaitEvent(p->cap_stream, p->ev_join, 0);
   hipError_t e2 = hipStreamEndCapture(p->cap_stream, &p->graph);
   if (e != hipSuccess) return fail(map_hip(e, "captured launch"));
   if ((rc = map_hip(e2, "end capture"))) return fail(rc);
@@ -546,6 +593,10 @@ int ctcalign_plan_destroy(ctcalign_plan* p) {
   if (p->d_trace) (void)hipFree(p->d_trace);
   if (p->d_order) (void)hipFree(p->d_order);
   if (p->d_head_long) (void)hipFree(p->d_head_long);
+  if (p->d_crit) (void)hipFree(p->d_crit);
+  if (p->crit_stream) (void)hipStreamDestroy(p->crit_stream);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   if (p->ctx && p->ctx->cached == p) p->ctx->cached = nullptr;
   delete p;
   return CTCALIGN_OK;

@@ -113,5 +113,9 @@ struct ctcalign_plan {
   int nlong = 0;                       // instances too large for packs (k_persistent_long)
   int* d_order = nullptr;              // their indices, longest first
   int* d_head_long = nullptr;
+  int ncrit = 0;                       // longest chains (k_persistent_crit, parallel branch)
+  int* d_crit = nullptr;
+  hipStream_t crit_stream = nullptr;   // capture-time only
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<int> pack_order_inst;    // first instance of each pack (host copy, for traces)
 };

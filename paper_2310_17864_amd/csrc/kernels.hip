@@ -177,6 +177,31 @@ __global__ void __launch_bounds__(512) k_persistent_long(const Inst* __restrict_
   }
 }
 
+// The longest chains of a batch: one alignment per 8-wave workgroup with few
+// states per lane (lower per-frame latency than a 4-wave pack), register
+// budget of 4 waves per SIMD so packs of the main kernel share the CU.  One
+// workgroup per alignment (no queue): the plan launches at most one per CU,
+// on a parallel branch of its graph, before the pack kernel.
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+k_persistent_crit(const Inst* __restrict__ insts, const int* __restrict__ order, int n) {
+  __shared__ SegSync sy[8];
+  __shared__ __attribute__((aligned(16))) float ring[8][kRing * kMaxC];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int item = blockIdx.x;
+  if (item >= n) return;
+  const Inst in = insts[order[item]];
+  if (w >= in.W) {
+    __syncthreads();   // the barrier the busy waves take inside run_wave
+    return;
+  }
+  reset_sync(sy + w, lane);
+  set_prio(in.prio);
+  switch (in.M) {
+    CTCA_CASE(4) CTCA_CASE(6) CTCA_CASE(8) CTCA_CASE(10) CTCA_CASE(12)
+    default: __syncthreads(); break;
+  }
+}
+
 #undef CTCA_CASE
 
 // ---- multi layout: one long alignment over several workgroups ---------------
@@ -392,6 +417,14 @@ hipError_t launch_persistent_long(const Inst* d_insts, const int* d_order, int n
                                   int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_persistent_long, dim3(grid), dim3(kWave * 8), 0, st, d_insts, d_order, n,
                      d_head);
+  return hipGetLastError();
+}
+
+static const int kCritMenu[] = {4, 6, 8, 10, 12};
+bool geometry_supported_crit(int W, int M) { return W >= 1 && W <= 8 && m_in(M, kCritMenu, 5); }
+
+hipError_t launch_persistent_crit(const Inst* d_insts, const int* d_order, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_persistent_crit, dim3(n), dim3(512), 0, st, d_insts, d_order, n);
   return hipGetLastError();
 }
 

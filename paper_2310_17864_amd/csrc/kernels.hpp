@@ -17,6 +17,9 @@ hipError_t launch_fill(int* p, int n, int v, hipStream_t st);
 hipError_t launch_persistent_long(const Inst* d_insts, const int* d_order, int n, int* d_head,
                                   int grid, hipStream_t st);
 bool geometry_supported_long_batch(int W, int M);
+// the batch's longest chains: one alignment per 8-wave workgroup, M in {4..12}
+bool geometry_supported_crit(int W, int M);
+hipError_t launch_persistent_crit(const Inst* d_insts, const int* d_order, int n, hipStream_t st);
 hipError_t launch_spans(const int32_t* path, const float* scores, int T, int blank, int max_spans,
                         int32_t* tok, int32_t* start, int32_t* end, float* score, int32_t* count,
                         hipStream_t st);

@@ -4,6 +4,7 @@
 // replaces the per-bucket choices with measured ones.
 #pragma once
 #include <stdint.h>
+#include <stdlib.h>
 
 #include <vector>
 
@@ -19,7 +20,8 @@ struct Geo {
 constexpr int kMenuOne[] = {2, 4, 6, 8, 10, 12, 14, 16};          // k_one, W <= 4
 constexpr int kMenuLong[] = {16, 24, 32, 40, 48, 56, 60, 64};     // k_one_long, W <= 8
 constexpr int kMenuPack[] = {2, 4, 6, 8, 10, 12, 14, 16};         // k_persistent, W in {1,2,4}
-constexpr int kMenuMulti[] = {8, 10, 12, 14, 16};                          // k_multi, 4 < W <= 64
+constexpr int kMenuMulti[] = {8, 10, 12, 14, 16};
+constexpr int kMenuCrit[] = {4, 6, 8, 10, 12};                      // k_persistent_crit, W <= 8                          // k_multi, 4 < W <= 64
 
 // Geometry is usable iff it covers S and the top segment holds S-1 and S-2
 // (the end-state choice reads both from one wavefront's registers).
@@ -33,7 +35,7 @@ struct TuneTable {
   // states-per-lane target for single launches and for packs (cost model:
   // per-frame time of a wave grows ~ 5.5*M + 12 VALU issues)
   int one_target_m = 6;
-  int pack_target_m = 8;
+  int pack_target_m = 12;
   // measured overrides, indexed by S bucket (S / 64) and stride class
   std::vector<Geo> one_override[2], pack_override[2];
 
@@ -46,7 +48,15 @@ struct TuneTable {
     for (int b = s_lo / kWave; b <= b1; ++b) t[b] = g;
   }
 
-  void load_default(int cus) { num_cu = cus > 0 ? cus : 256; }
+  // Defaults, then optional overrides from the environment:
+  // CTCALIGN_PACK_TARGET_M, CTCALIGN_CRIT_FRAC (0 disables the critical-chain
+  // kernel), CTCALIGN_CRIT_PER_CU.
+  void load_default(int cus) {
+    num_cu = cus > 0 ? cus : 256;
+    if (const char* v = std::getenv("CTCALIGN_PACK_TARGET_M")) pack_target_m = std::atoi(v);
+    if (const char* v = std::getenv("CTCALIGN_CRIT_FRAC")) crit_frac = std::atof(v);
+    if (const char* v = std::getenv("CTCALIGN_CRIT_PER_CU")) crit_per_cu = std::atof(v);
+  }
 
   static int cls(int C) { return C <= 32 ? 0 : 1; }
 
@@ -104,6 +114,19 @@ struct TuneTable {
   // Largest trellis for the pack kernel: every S up to 4 * 64 * 16 has a
   // pack layout (W <= 4 covers them all; W = 8 layouts leave gaps above).
   int64_t max_pack_states() const { return 4 * kWave * 16; }
+
+  // Chain latency model (ns per frame of one alignment, measured alone on
+  // MI355X: about 190 + 16 M) and the critical-chain selection.
+  double chain_ns(const Inst& in) const { return (double)in.T * (190.0 + 16.0 * in.M); }
+  double crit_frac = 0.6;
+  double crit_per_cu = 1.0;
+  int crit_max() const { return crit_frac > 0 ? (int)(crit_per_cu * num_cu) : 0; }
+  Geo pick_crit(int S) const {
+    for (int M : kMenuCrit)
+      for (int W = 1; W <= 8; ++W)
+        if (geo_ok(S, W, M)) return Geo{W, M};
+    return Geo{0, 0};
+  }
 
   // relative time of one frame on one wave
   double step_cost(Geo g, int stride) const { return 5.5 * g.M + 12.0 + (stride > 32 ? 2.0 : 0.0); }
