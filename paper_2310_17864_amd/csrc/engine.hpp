@@ -98,20 +98,16 @@ __device__ __forceinline__ bool wait_geq(int* p, int need) {
 // a[j] holds a_{t-1} for state sbase+j on entry and a_t on exit.  States are
 // updated from the top down so every read sees a_{t-1}.  nb is a_{t-1} of the
 // state just below this lane's first one.  Even slots are blank states.
-// Skip permission of label slot jj: for M <= 16 a lane mask per slot (kept in
-// SGPRs, ANDed with the compare mask by the scalar unit); for larger M, where
-// the masks would not fit the SGPR file, a per-lane additive penalty (0 or
-// -inf) folded into the compared value -- the compare result is the same and
-// the selected value stays the unmodified a_{t-1}(s-2).
-template <int M>
-struct SkipRep {
-  static constexpr bool kMask = M <= 16;
-  using T = typename std::conditional<kMask, uint64_t, float>::type;
-};
+// Skip permission of label slot jj: a per-lane additive penalty (0 or -inf)
+// folded into the compared value -- the compare result is that of the masked
+// compare and the selected value stays the unmodified a_{t-1}(s-2).  (A lane
+// mask ANDed by the scalar unit costs fewer VALU issues but puts a VALU ->
+// SALU -> VALU round trip into every label state's chain: the per-frame
+// latency of one wave measured ~15 % higher.)
 
 template <int M>
 __device__ __forceinline__ void dp_frame(float (&a)[M], uint32_t (&acc)[bp_words_per_lane(M)],
-                                         const typename SkipRep<M>::T (&skip)[M / 2], float nbs,
+                                         const float (&skip)[M / 2], float nbs,
                                          float nb_in, float eb, const float (&e)[M / 2]) {
   // lane 0 takes the boundary value from below; selected only where the two
   // lowest states use it, so its LDS read may still be in flight until then
@@ -122,21 +118,17 @@ __device__ __forceinline__ void dp_frame(float (&a)[M], uint32_t (&acc)[bp_words
     if (j % 2 == 0) {
       const uint64_t c1 = gt_mask(p1, a[j]);
       const float best = sel(c1, p1, a[j]);
-      acc[plane_mv(M, j) / 4] = shift_in(acc[plane_mv(M, j) / 4], c1);
+      acc[plane_word(M, plane_mv(M, j))] = shift_in(acc[plane_word(M, plane_mv(M, j))], c1);
       a[j] = eb + best;
     } else {
       const float p2 = (j >= 2) ? a[j - 2] : nb;
       const uint64_t c1 = gt_mask(p1, a[j]);
       const float b1 = sel(c1, p1, a[j]);
-      uint64_t c2;
-      if constexpr (SkipRep<M>::kMask)
-        c2 = gt_mask(p2, b1) & skip[j / 2];
-      else
-        c2 = gt_mask(p2 + skip[j / 2], b1);
+      const uint64_t c2 = gt_mask(p2 + skip[j / 2], b1);
       const float b2 = sel(c2, p2, b1);
       // moved before skipped: planes are numbered in shift-in order
-      acc[plane_mv(M, j) / 4] = shift_in(acc[plane_mv(M, j) / 4], c1);
-      acc[plane_sk(M, j) / 4] = shift_in(acc[plane_sk(M, j) / 4], c2);
+      acc[plane_word(M, plane_mv(M, j))] = shift_in(acc[plane_word(M, plane_mv(M, j))], c1);
+      acc[plane_word(M, plane_sk(M, j))] = shift_in(acc[plane_word(M, plane_sk(M, j))], c2);
       a[j] = e[j / 2] + b2;
     }
   }
@@ -297,7 +289,7 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   // ring at byte offset 4*label; padding states (s >= S) read the blank
   // column and can neither skip nor feed a real state.
   int eoff[M / 2];
-  typename SkipRep<M>::T skip[M / 2];   // may enter from two states below
+  float skip[M / 2];   // 0: may enter from two states below, -inf: may not
 #pragma unroll
   for (int jj = 0; jj < M / 2; ++jj) {
     const int s = sbase + 2 * jj + 1;
@@ -308,10 +300,7 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
       if (s >= 3) sk = lab != in.lab[(s - 3) / 2];
     }
     eoff[jj] = lab;
-    if constexpr (SkipRep<M>::kMask)
-      skip[jj] = __builtin_amdgcn_ballot_w64(sk);
-    else
-      skip[jj] = sk ? 0.0f : neg_inf();
+    skip[jj] = sk ? 0.0f : neg_inf();
   }
 
   // a3: frame 0.  Only states 0 and 1 start finite.
@@ -616,11 +605,11 @@ __device__ __forceinline__ PlaneLoc plane_loc(int q) {
   p.odd = j % 2;
   const int pmv = plane_mv(M, j);
   const int psk = p.odd ? plane_sk(M, j) : pmv;
-  p.qm = pmv / 4;
-  p.pm = pmv % 4;
+  p.qm = plane_word(M, pmv);
+  p.pm = plane_pos(M, pmv);
   p.rm = planes_in_word(M, p.qm);
-  p.qs = psk / 4;
-  p.ps = psk % 4;
+  p.qs = plane_word(M, psk);
+  p.ps = plane_pos(M, psk);
   p.rs = planes_in_word(M, p.qs);
   return p;
 }

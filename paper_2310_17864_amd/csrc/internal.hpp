@@ -72,11 +72,13 @@ struct PadDesc {
 // Backpointer layout.  Frames 1..T-1 carry backpointers, in groups of 8
 // frames.  Per state slot a lane produces one "moved" bit (came from s-1 or
 // s-2) and, for label slots, one "skipped" bit (came from s-2).  A lane's
-// 3M/2 bit planes are numbered in the order the forward pass produces them
+// P = 3M/2 bit planes are numbered in the order the forward pass produces them
 // (slot pairs from the top down: moved(odd), skipped(odd), moved(even)) and
-// packed four planes per 32-bit word, interleaved by frame: in word q, which
-// holds R = min(4, 3M/2 - 4q) planes, plane 4q+r at frame i of the group sits
-// at bit 31 - (R*i + r).  Words are stored [segment][group][word][lane].
+// dealt round-robin over its NQ = ceil(P/4) words (plane p -> word p % NQ,
+// position p / NQ), so consecutive planes land in different words and their
+// shift-ins do not wait on each other.  Word q holds R_q planes interleaved by
+// frame: the plane at position r, frame i of the group sits at bit
+// 31 - (R_q*i + r).  Words are stored [segment][group][word][lane].
 __host__ __device__ constexpr int bp_planes(int M) { return 3 * M / 2; }
 __host__ __device__ constexpr int bp_words_per_lane(int M) { return (bp_planes(M) + 3) / 4; }
 __host__ __device__ inline int64_t bp_groups(int64_t T) { return (T - 1 + kUnroll - 1) / kUnroll; }
@@ -89,7 +91,9 @@ __host__ __device__ constexpr int plane_mv(int M, int j) {
 }
 __host__ __device__ constexpr int plane_sk(int M, int j) { return 3 * (M / 2 - 1 - j / 2) + 1; }
 __host__ __device__ constexpr int planes_in_word(int M, int q) {
-  return (bp_planes(M) - 4 * q) < 4 ? (bp_planes(M) - 4 * q) : 4;
+  return (bp_planes(M) - q + bp_words_per_lane(M) - 1) / bp_words_per_lane(M);
 }
+__host__ __device__ constexpr int plane_word(int M, int p) { return p % bp_words_per_lane(M); }
+__host__ __device__ constexpr int plane_pos(int M, int p) { return p / bp_words_per_lane(M); }
 
 }  // namespace ctca
