@@ -24,6 +24,37 @@ namespace {
 std::mutex g_default_mu;
 ctcalign_ctx* g_default[kMaxDevices] = {};
 
+// Sync region of multi-workgroup alignments, one per device, in uncached
+// device memory: workgroups on different XCDs poll it, and a cached copy of a
+// line in one XCD's L2 (left there by the reset kernel) would hide the other
+// XCDs' writes.  Kept for the life of the process (uncached memory is never
+// freed once a kernel has read it).  Launches that use it are serialised with
+// an event, whatever stream they come on.
+struct MultiSync {
+  std::mutex mu;
+  XSync* region = nullptr;
+  hipEvent_t last = nullptr;
+  bool used = false;
+};
+MultiSync g_msync[kMaxDevices];
+
+int launch_multi_serial(int device, const Inst& in, hipStream_t st) {
+  if (device < 0 || device >= kMaxDevices) return CTCALIGN_EDEVICE;
+  MultiSync& m = g_msync[device];
+  std::lock_guard<std::mutex> lk(m.mu);
+  if (!m.region) {
+    void* p = nullptr;
+    HIP_TRY(hipExtMallocWithFlags(&p, sizeof(XSync), hipDeviceMallocUncached));
+    m.region = static_cast<XSync*>(p);
+    HIP_TRY(hipEventCreateWithFlags(&m.last, hipEventDisableTiming));
+  }
+  if (m.used) HIP_TRY(hipStreamWaitEvent(st, m.last, 0));
+  HIP_TRY(launch_multi(in, m.region, st));
+  HIP_TRY(hipEventRecord(m.last, st));
+  m.used = true;
+  return CTCALIGN_OK;
+}
+
 int validate_one(const float* em, int32_t T, int32_t C, const int32_t* labels, int32_t L,
                  int32_t blank, const void* path, const void* scores) {
   if (!em || !path || !scores) return CTCALIGN_EINVAL;
@@ -63,9 +94,8 @@ int launch_single(ctcalign_ctx* ctx, const float* emission, int32_t T, int32_t C
   geometry_one(ctx, in);
   if (!geometry_supported_one(in.W, in.M) || !geo_ok(2 * L + 1, in.W, in.M)) return CTCALIGN_EINVAL;
 
-  const size_t bp_need = round_up((size_t)bp_words(T, in.W, in.M) * 4, 256);
+  const size_t need = round_up((size_t)bp_words(T, in.W, in.M) * 4, 256);
   const bool multi = geometry_is_multi(in.W, in.M);
-  const size_t need = bp_need + (multi ? round_up(sizeof(XSync), 256) : 0);
   char* ws;
   if (workspace) {
     if (ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255u)) return CTCALIGN_EINVAL;
@@ -76,7 +106,6 @@ int launch_single(ctcalign_ctx* ctx, const float* emission, int32_t T, int32_t C
     ws = static_cast<char*>(ctx->ws.ptr);
   }
   in.bp = reinterpret_cast<uint32_t*>(ws);
-  XSync* xs = multi ? reinterpret_cast<XSync*>(ws + bp_need) : nullptr;
 
   if (C == in.stride && aligned16(emission)) {
     in.em = emission;
@@ -89,7 +118,8 @@ int launch_single(ctcalign_ctx* ctx, const float* emission, int32_t T, int32_t C
     in.em = static_cast<float*>(ctx->pad.ptr);
   }
   CTCA_LOG(2, "align T=%d C=%d L=%d -> W=%d M=%d stride=%d", T, C, L, in.W, in.M, in.stride);
-  HIP_TRY(multi ? launch_multi(in, xs, st) : launch_one(in, st));
+  if (multi) return launch_multi_serial(ctx->device, in, st);
+  HIP_TRY(launch_one(in, st));
   return CTCALIGN_OK;
 }
 
@@ -241,8 +271,7 @@ int ctcalign_ctx_destroy(ctcalign_ctx* c) {
 size_t ctcalign_workspace_bytes(ctcalign_ctx* ctx, int32_t T, int32_t L, int32_t C) {
   if (!ctx || T < 1 || L < 0 || C < 1 || C > kMaxC || 2 * (int64_t)L + 1 > kMaxS) return 0;
   const Geo g = ctx->tune.pick_one(2 * L + 1, C);
-  return round_up((size_t)bp_words(T, g.W, g.M) * 4, 256) +
-         (geometry_is_multi(g.W, g.M) ? round_up(sizeof(XSync), 256) : 0);
+  return round_up((size_t)bp_words(T, g.W, g.M) * 4, 256);
 }
 
 int ctcalign_align_ex(ctcalign_ctx* ctx, const float* emission, int32_t T, int32_t C,

@@ -217,10 +217,10 @@ struct XLink {
 constexpr int kXSpinLimit = 1 << 20;
 
 __device__ __forceinline__ uint64_t x_load(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ void x_store(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Copies boundary values i0 .. i0+cnt-1 (cnt <= 64) from the global ring to
@@ -234,7 +234,7 @@ __device__ __forceinline__ bool x_pull(XChan* ch, SegSync* dst, int i0, int cnt,
     const bool ok = lane >= cnt || (int32_t)(v >> 32) == i;
     if (__builtin_amdgcn_ballot_w64(!ok) == 0) {
       if (lane < cnt) dst->bnd[i % kBnd] = __builtin_bit_cast(float, (uint32_t)v);
-      if (lane == 0) __hip_atomic_store(&ch->cons, i0 + cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0) __hip_atomic_store(&ch->cons, i0 + cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       return true;
     }
     __builtin_amdgcn_s_sleep(2);
@@ -246,7 +246,7 @@ __device__ __forceinline__ bool x_pull(XChan* ch, SegSync* dst, int i0, int cnt,
 // up to index i_end (exclusive) would overwrite.  `seen` caches its progress.
 __device__ __forceinline__ bool x_room(XChan* ch, int i_end, int& seen) {
   for (int it = 0; it < kXSpinLimit && i_end - kXRing > seen; ++it) {
-    seen = __hip_atomic_load(&ch->cons, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    seen = __hip_atomic_load(&ch->cons, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     if (i_end - kXRing > seen) __builtin_amdgcn_s_sleep(2);
   }
   return i_end - kXRing <= seen;

@@ -37,10 +37,10 @@ struct Inst {
 // different workgroups exchange boundary values through a ring of 64-bit
 // slots in global memory, each holding (value bits, frame index) so that a
 // reader recognises a slot written for the index it wants; all accesses are
-// agent-scope relaxed atomics.  The region sits after the backpointers in
-// the workspace and is reset (every word -1) before each launch.
+// relaxed atomics.  The region lives in uncached device memory (one per
+// device) and is reset (every word -1) before each launch.
 constexpr int kXWaves = 8;        // waves per workgroup
-constexpr int kXMaxGroups = 8;    // workgroups per alignment
+constexpr int kXMaxGroups = 32;   // workgroups per alignment
 constexpr int kXRing = 512;       // slots per cross-workgroup boundary
 struct XChan {
   uint64_t slot[kXRing];

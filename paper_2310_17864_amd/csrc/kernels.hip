@@ -208,7 +208,7 @@ k_persistent_crit(const Inst* __restrict__ insts, const int* __restrict__ order,
 
 __device__ __forceinline__ bool wait_geq_agent(int* p, int need) {
   for (int n = 0; n < kXSpinLimit; ++n) {
-    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return true;
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) >= need) return true;
     __builtin_amdgcn_s_sleep(2);
   }
   return false;
@@ -228,7 +228,7 @@ __device__ __forceinline__ void run_multi(const Inst& in, XSync* xs, SegSync* sy
   if (w + 1 < in.W) {
     // backpointers visible device-wide, then the flag
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (lane == 0) __hip_atomic_store(&xs->done[w], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) __hip_atomic_store(&xs->done[w], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   } else {
     bool ok = fo.ok != 0;
     for (int k = 0; k + 1 < in.W; ++k) ok &= wait_geq_agent(&xs->done[k], 1);
@@ -258,6 +258,9 @@ __global__ void __launch_bounds__(kWave * kXWaves) k_multi(Inst in, XSync* xs) {
   const int g = blockIdx.x;
   const Ring r{ring[wl]};
   switch (in.M) {
+    case 2: run_multi<2>(in, xs, sy, r, g, wl, lane, bad); break;
+    case 4: run_multi<4>(in, xs, sy, r, g, wl, lane, bad); break;
+    case 6: run_multi<6>(in, xs, sy, r, g, wl, lane, bad); break;
     case 8: run_multi<8>(in, xs, sy, r, g, wl, lane, bad); break;
     case 10: run_multi<10>(in, xs, sy, r, g, wl, lane, bad); break;
     case 12: run_multi<12>(in, xs, sy, r, g, wl, lane, bad); break;
@@ -358,11 +361,11 @@ static const int kOneMenu[] = {2, 4, 6, 8, 10, 12, 14, 16};
 static const int kLongMenu[] = {16, 24, 32, 40, 48, 56, 60, 64};
 static const int kPackMenuK[] = {2, 4, 6, 8, 10, 12, 14, 16};
 
-static const int kMultiMenu[] = {8, 10, 12, 14, 16};
+static const int kMultiMenu[] = {2, 4, 6, 8, 10, 12, 14, 16};
 
 bool geometry_supported_one(int W, int M) {
   if (W >= 1 && W <= 4 && m_in(M, kOneMenu, 8)) return true;
-  if (geometry_is_multi(W, M) && W <= kXWaves * kXMaxGroups && m_in(M, kMultiMenu, 5)) return true;
+  if (geometry_is_multi(W, M) && W <= kXWaves * kXMaxGroups && m_in(M, kMultiMenu, 8)) return true;
   if (W >= 1 && W <= 8 && m_in(M, kLongMenu, 8)) return true;
   return false;
 }
@@ -386,8 +389,13 @@ hipError_t launch_multi(const Inst& in, XSync* xs, hipStream_t st) {
   hipLaunchKernelGGL(k_fill, dim3((nwords + 255) / 256), dim3(256), 0, st, reinterpret_cast<int*>(xs),
                      nwords, -1);
   const int groups = (in.W + kXWaves - 1) / kXWaves;
-  hipLaunchKernelGGL(k_multi, dim3(groups), dim3(kWave * kXWaves), 0, st, in, xs);
-  return hipGetLastError();
+  // the workgroups wait on each other: a cooperative launch guarantees they
+  // are all resident at once (or fails instead of starting)
+  Inst in_copy = in;
+  XSync* xs_copy = xs;
+  void* args[] = {&in_copy, &xs_copy};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_multi), dim3(groups),
+                                    dim3(kWave * kXWaves), args, 0, st);
 }
 
 hipError_t launch_persistent(const Inst* d_insts, const Pack* d_packs, int npacks, int* d_head,

@@ -20,7 +20,7 @@ struct Geo {
 constexpr int kMenuOne[] = {2, 4, 6, 8, 10, 12, 14, 16};          // k_one, W <= 4
 constexpr int kMenuLong[] = {16, 24, 32, 40, 48, 56, 60, 64};     // k_one_long, W <= 8
 constexpr int kMenuPack[] = {2, 4, 6, 8, 10, 12, 14, 16};         // k_persistent, W in {1,2,4}
-constexpr int kMenuMulti[] = {8, 10, 12, 14, 16};
+constexpr int kMenuMulti[] = {2, 4, 6, 8, 10, 12, 14, 16};
 constexpr int kMenuCrit[] = {4, 6, 8, 10, 12};                      // k_persistent_crit, W <= 8                          // k_multi, 4 < W <= 64
 
 // Geometry is usable iff it covers S and the top segment holds S-1 and S-2

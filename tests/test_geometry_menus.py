@@ -37,8 +37,9 @@ def test_single_menus_cover_all_sizes():
 def test_multi_menu_covers_long_single_launches():
     # single launches above 4096 states use the multi-workgroup layout: the
     # chooser takes W = ceil(S / (64 M)) for the first M of the menu that
-    # holds S; every odd S (S = 2L + 1) up to 32768 must find one with W <= 64
+    # holds S; every odd S (S = 2L + 1) up to 32768 must find one with W <= 256
+    # (32 workgroups of 8 waves)
     multi = menu("kMenuMulti")
     gaps = [S for S in range(4097, 32769, 2)
-            if not any(geo_ok(S, -(-S // (64 * M)), M) and -(-S // (64 * M)) <= 64 for M in multi)]
+            if not any(geo_ok(S, -(-S // (64 * M)), M) and -(-S // (64 * M)) <= 256 for M in multi)]
     assert gaps == []
