@@ -249,7 +249,8 @@ def run_batched(args):
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "roofline": {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": hbm / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_persistent (graph: queue reset + persistent kernel)",
+                     "kernel": "graph replay: k_persistent (packs) and k_persistent_crit (longest "
+                               "chains) running concurrently; time = the replay",
                      "bytes_per_launch": bytes_alg},
         "alu": {"achieved_ops_per_s": alu, "peak_ops_per_s": VALU_PEAK_OPS,
                 "frac": alu / VALU_PEAK_OPS, "ops_per_launch": ops_alg},

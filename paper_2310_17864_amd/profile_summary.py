@@ -56,34 +56,48 @@ def stats(d: str, out: str, command: str, top: int = 12) -> None:
     print("\n".join(lines))
 
 
-def _per_dispatch(path: str, counter: str, pattern: str):
+def _per_kernel(path: str, counter: str, pattern: str):
+    """{kernel name: (median per-dispatch value, dispatches)} for kernels whose
+    name contains `pattern`."""
     vals = {}
+    names = {}
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter or pattern not in r["Kernel_Name"]:
             continue
         d = r["Dispatch_Id"]
         vals[d] = vals.get(d, 0.0) + float(r["Counter_Value"])
+        names[d] = r["Kernel_Name"].split("(")[0]
     if not vals:
         raise SystemExit(f"no {counter} rows for kernels matching {pattern!r} in {path}")
-    return statistics.median(vals.values()), len(vals)
+    by = {}
+    for d, v in vals.items():
+        by.setdefault(names[d], []).append(v)
+    return {k: (statistics.median(v), len(v)) for k, v in by.items()}
 
 
 def traffic(fetch_dir: str, write_dir: str, out: str, copy_bytes: int, command: str,
-            kernel: str = "k_persistent", copy_kernel: str = "neg") -> None:
+            kernel: str = "ctca::k_persistent", copy_kernel: str = "elementwise") -> None:
+    """One replay of a plan runs each matching kernel once (the pack kernel and
+    the critical-chain kernel, concurrently): its traffic is the sum of their
+    per-dispatch medians."""
     fpath, wpath = _find(fetch_dir, "counter_collection.csv"), _find(write_dir, "counter_collection.csv")
-    fk, nf = _per_dispatch(fpath, "FETCH_SIZE", kernel)
-    wk, nw = _per_dispatch(wpath, "WRITE_SIZE", kernel)
-    cf, _ = _per_dispatch(fpath, "FETCH_SIZE", copy_kernel)
-    cw, _ = _per_dispatch(wpath, "WRITE_SIZE", copy_kernel)
-    lines = ["# HBM traffic of the persistent alignment kernel, rocprofv3 --pmc (KiB per dispatch,",
-             "# median over dispatches), with a plain copy of copy_bytes bytes as the scale",
+    fk = _per_kernel(fpath, "FETCH_SIZE", kernel)
+    wk = _per_kernel(wpath, "WRITE_SIZE", kernel)
+    cf = sum(v for v, _ in _per_kernel(fpath, "FETCH_SIZE", copy_kernel).values())
+    cw = sum(v for v, _ in _per_kernel(wpath, "WRITE_SIZE", copy_kernel).values())
+    fsum = sum(v for v, _ in fk.values())
+    wsum = sum(v for v, _ in wk.values())
+    lines = ["# HBM traffic of one plan replay (its kernels' per-dispatch medians, summed),",
+             "# rocprofv3 --pmc, KiB per dispatch, with a plain copy of copy_bytes bytes as the scale",
              f"# command (FETCH_SIZE, then WRITE_SIZE in a second run): {command}",
-             f"kernel_source_hash = {kernel_source_hash()}",
-             f"kernel = {kernel}", f"dispatches = {min(nf, nw)}",
-             f"fetch_kb = {fk:.1f}", f"write_kb = {wk:.1f}",
-             f"copy_bytes = {copy_bytes}", f"copy_fetch_kb = {cf:.1f}", f"copy_write_kb = {cw:.1f}",
-             f"# scaled: read {fk * copy_bytes / cf / 1e9:.3f} GB, write {wk * copy_bytes / cw / 1e9:.3f} GB"
-             " per dispatch"]
+             f"kernel_source_hash = {kernel_source_hash()}"]
+    for k in sorted(fk):
+        lines.append(f"# {k}: fetch {fk[k][0]:.1f} KiB, write {wk.get(k, (0, 0))[0]:.1f} KiB "
+                     f"({fk[k][1]} dispatches)")
+    lines += [f"fetch_kb = {fsum:.1f}", f"write_kb = {wsum:.1f}",
+              f"copy_bytes = {copy_bytes}", f"copy_fetch_kb = {cf:.1f}", f"copy_write_kb = {cw:.1f}",
+              f"# scaled: read {fsum * copy_bytes / cf / 1e9:.3f} GB, write {wsum * copy_bytes / cw / 1e9:.3f} GB"
+              " per replay"]
     open(out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
