@@ -130,7 +130,12 @@ int ctcalign_align(const float *emission, int32_t T, int32_t C,
  * workspace (device, >= ctcalign_workspace_bytes, 256-byte aligned) may be
  * NULL: the context's arena is used (then calls on one context serialise on
  * its arena).  Returns OK when the launch was queued; the alignment's own
- * status is written to *out_status. */
+ * status is written to *out_status.
+ * Trellises above 4096 states run over several workgroups that exchange
+ * boundary values through a per-device sync region: such launches are
+ * cooperative, are serialised with each other across streams by an event
+ * (so they cannot be captured into a HIP graph), and fail with EDEVICE if
+ * the workgroups cannot all be resident. */
 int ctcalign_align_ex(ctcalign_ctx *ctx, const float *emission, int32_t T, int32_t C,
                       const int32_t *labels, int32_t L, int32_t blank,
                       int32_t *out_path, float *out_scores, float *out_total,

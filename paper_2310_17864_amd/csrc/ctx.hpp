@@ -51,6 +51,8 @@ struct Arena {
   int reserve(size_t need) {
     if (need <= bytes) return CTCALIGN_OK;
     if (ptr) {
+      // launches queued earlier may still use the old buffer
+      (void)hipDeviceSynchronize();
       (void)hipFree(ptr);
       ptr = nullptr;
       bytes = 0;

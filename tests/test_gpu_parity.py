@@ -171,3 +171,35 @@ def test_multi_workgroup_layouts(L, T):
     r = np.random.default_rng(L)
     u = synth.utterance(r, T, 32 if L % 2 else 256, L, 0, 6.0, 1.0, 0.1)
     assert compare_one(u.emission, u.labels, 0, f"multiL{L}") == []
+
+
+def test_multi_workgroup_repeated_launches():
+    # back-to-back asynchronous launches of multi-workgroup alignments of
+    # different sizes on one stream, interleaved with a batched plan: every
+    # run completes (no bounded wait runs out) and equals the oracle.  (The
+    # cross-workgroup slots were once read through a stale cache line left by
+    # the reset of an earlier launch.)
+    import paper_2310_17864_amd as ca
+    from gpu_util import torch_dev
+    torch, dev = torch_dev()
+    cases = []
+    for seed, (L, T) in enumerate([(2500, 5100), (7000, 14100), (15000, 30200)]):
+        u = synth.utterance(np.random.default_rng(100 + seed), T, 32, L, 0, 6.0, 1.0, 0.1)
+        st, p, s, t = oracle.align_f32(u.emission, u.labels, 0)
+        cases.append((torch.from_numpy(u.emission).to(dev), torch.from_numpy(u.labels).to(dev), st, p, s))
+    wl = synth.cfg_batched(n=32, t_hi=1500, seed=9)
+    pk = synth.pack(wl.utts)
+    plan = ca.Plan(torch.from_numpy(pk["em"]).to(dev), pk["em_off"], pk["T"], pk["C"],
+                   torch.from_numpy(pk["lab"]).to(dev), pk["lab_off"], pk["L"], pk["fr_off"], 0)
+    outs = []
+    for rep in range(3):
+        for e, y, _, _, _ in cases:
+            outs.append(ca.align(e, y, 0, sync=False))
+        plan.run()
+    torch.cuda.synchronize()
+    for k, (path, scores, total, status) in enumerate(outs):
+        _, _, st, p, s = cases[k % len(cases)]
+        assert int(status.item()) == st == 0, k
+        assert np.array_equal(path.cpu().numpy(), p), k
+        assert np.array_equal(scores.cpu().numpy().view(np.uint32), s.view(np.uint32)), k
+    plan.close()
