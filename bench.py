@@ -457,7 +457,7 @@ def main():
     ap.add_argument("--workload", default="batched", choices=["batched", "long", "single", "serve"])
     ap.add_argument("--n", type=int, default=4096, help="utterances in the batched workload")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="open-loop serving run after the batched bench (0: skip)")
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--pool", type=int, default=1024)

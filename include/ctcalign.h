@@ -241,22 +241,30 @@ typedef struct ctcalign_server_stats {
  * backpointer memory, T*(2L+1)/4 bytes (or its actual workspace if larger),
  * against bp_budget_bytes; requests are admitted in arrival order (FIFO)
  * while the charge in flight stays within the budget and fewer than
- * max_inflight requests are on the device; admitted requests are launched
- * together and overlap with groups admitted earlier or later.
- * Errors: EINVAL, ENOMEM (arena), EDEVICE. */
+ * max_inflight requests are on the device.  Admitted requests run on a
+ * resident kernel (one 16-wave workgroup per compute unit) that the server
+ * keeps on its own stream while there is work and stops about 20 ms after
+ * the last request; each request completes on its own, as soon as its
+ * alignment is written.  While that kernel is resident, kernels the caller
+ * queues on a stream that shares its hardware queue wait for it to stop.
+ * Requests hold up to S = 2L+1 = 16384 states.
+ * Errors: EINVAL, ENOMEM (arena or pinned host memory), EDEVICE. */
 int ctcalign_server_create(ctcalign_ctx *ctx, size_t bp_budget_bytes, int32_t max_inflight,
                            ctcalign_server **server);
 
-/* Queues a request (never blocks).  *ticket identifies it.  Errors: EINVAL
- * (bad arguments; the request is not queued), ENOMEM (its charge alone
+/* Queues a request (never blocks).  *ticket identifies it.  The emission and
+ * labels must be written, and no other work may write the outputs, before
+ * the call (the request may start at once).  Errors: EINVAL (bad arguments
+ * or 2L+1 > 16384; the request is not queued), ENOMEM (its charge alone
  * exceeds the budget), EAGAIN (queue full). */
 int ctcalign_server_submit(ctcalign_server *server, const ctcalign_request *req, uint64_t *ticket);
 
 /* Non-blocking completion check.  EBUSY while pending; OK once done, with
  * *status the alignment's own status (OK, EINVAL, EINFEASIBLE, or EDEVICE if
- * the watchdog gave up on its launch) and *timing filled (either may be
- * NULL).  A completed ticket is consumed by the call; EINVAL for an unknown
- * or consumed ticket. */
+ * the watchdog gave up on it after 30 s or the kernel could not be launched)
+ * and *timing filled (either may be NULL); the outputs are then written and
+ * visible to any later work on the device.  A completed ticket is consumed by
+ * the call; EINVAL for an unknown or consumed ticket. */
 int ctcalign_server_poll(ctcalign_server *server, uint64_t ticket, int32_t *status,
                          ctcalign_timing *timing);
 

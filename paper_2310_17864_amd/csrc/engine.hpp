@@ -504,6 +504,18 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
     if (S == 1) {
       out.total = f1;
       out.send = 0;
+    } else if (q1 == 0) {
+      // S-1 opens this segment (layouts whose top segment holds one state):
+      // S-2 is the last state of the segment below, and its value at the
+      // last frame is the final entry of the boundary ring, which the last
+      // block already waited for (with one frame there is no ring entry, and
+      // a_0(S-2) = -inf since S-2 >= 2)
+      float f2 = neg_inf();
+      if (prev_x) out.ok = 0;   // not a layout of the multi-workgroup kernel
+      else if (in.T > 1) f2 = pv->bnd[(in.T - 1) % kBnd];
+      const bool take2 = f2 > f1;
+      out.total = take2 ? f2 : f1;
+      out.send = take2 ? S - 2 : S - 1;
     } else {
       const int q2 = q1 - 1;
       const int l2 = q2 / M;
@@ -835,6 +847,13 @@ __device__ __forceinline__ void backtrack(const Inst& in, const FwdOut& fo, int 
   if (lane == 0) {
     if (in.total) *in.total = total;
     if (in.status) *in.status = status;
+  }
+  if (in.notify) {
+    // every store of this wave (path, scores, total, status) complete and
+    // written back past the L2 before the flag reaches the host
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    if (lane == 0) __hip_atomic_store(in.notify, status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 

@@ -26,6 +26,9 @@ struct Inst {
   uint32_t* bp;        // backpointer planes, bp_words(T, W, M) words
   float* total;        // nullable
   int32_t* status;     // nullable
+  int32_t* notify;     // nullable: host-visible completion flag (fine-grained
+                       // pinned host memory), set to the status after every
+                       // output of the alignment is written and visible
   int32_t T, C, L, blank;
   int32_t W, M;        // geometry
   int32_t stride;      // emission row stride in HBM and LDS: 32 or 256
@@ -67,6 +70,29 @@ struct PadDesc {
   const float* src;   // [T][C]
   float* dst;         // [T][stride]
   int32_t T, C, stride, pad_;
+};
+
+// Resident serving kernel: one 16-wave workgroup per CU stays on the device
+// and runs work items the host posts to it.  Everything the two sides share
+// lives in fine-grained pinned host memory; the device only loads from it
+// and stores to it (no read-modify-write), so there is no cross-workgroup
+// atomic on the device at all.
+constexpr int kServeWaves = 16;
+struct ServeItem {                // one workgroup's work: up to 16 segments
+  Inst inst[kServeWaves];         // the item's alignments
+  int8_t which[kServeWaves];      // wave -> index into inst (-1: idle wave)
+  int8_t seg[kServeWaves];        // wave -> segment of that alignment
+  int8_t first[kServeWaves];      // wave -> first wave of that alignment
+  int32_t npad;                   // 1: copy pad.src into pad.dst (inst[0]'s rows) first
+  int32_t pad1_;
+  PadDesc pad;
+};
+static_assert(sizeof(ServeItem) % 8 == 0, "items are copied in 8-byte words");
+struct ServeBox {                 // per resident workgroup b (host memory)
+  uint64_t mail;                  // host -> device: (sequence << 32) | 0, item in items[b]
+  uint64_t ack;                   // device -> host: sequence of the last finished item
+  uint64_t live;                  // device -> host: launch epoch once the workgroup runs
+  uint64_t pad_[5];               // own 64-byte line
 };
 
 // Backpointer layout.  Frames 1..T-1 carry backpointers, in groups of 8

@@ -26,5 +26,10 @@ hipError_t launch_spans(const int32_t* path, const float* scores, int T, int bla
 hipError_t launch_pad(const PadDesc* d_desc, int n, int64_t max_elems, hipStream_t st);
 hipError_t launch_pad_one(const PadDesc& pd, hipStream_t st);
 int persistent_blocks_per_cu();
+// resident serving kernel: `grid` 16-wave workgroups serving the mailboxes
+// d_box[0..grid) with items d_items[0..grid) (all in mapped host memory)
+hipError_t launch_serve(const ServeItem* d_items, ServeBox* d_box, const int32_t* d_stop,
+                        uint64_t epoch, int64_t idle_limit, int grid, hipStream_t st);
+bool geometry_supported_serve(int W, int M);
 
 }  // namespace ctca

@@ -4,6 +4,11 @@
 // group of admitted requests and later reports them done, so the same logic
 // runs against the GPU executor (server.cpp) and a CPU fake (tests).
 //
+// Requests of one launch finish one by one: the executor reports each
+// request's status as soon as its alignment is written, and the scheduler
+// then reports it and frees its memory, without waiting for the rest of the
+// launch.
+//
 // Admission is strictly FIFO: the oldest waiting request is admitted as soon
 // as (a) fewer than max_inflight requests are on the device, (b) its charge
 // fits the budget next to everything in flight, and (c) its workspace fits a
@@ -81,6 +86,43 @@ class ArenaMap {
   size_t size_ = 0, used_ = 0;
 };
 
+// Workgroup packs of kWaves waves for a group of small alignments: an
+// alignment of W waves (W divides kWaves) takes W consecutive waves of a
+// pack, kWaves / W alignments of one width share a pack, widest first.  Wave
+// k of a pack runs segment seg[k] of alignment inst[k] (-1: idle) whose first
+// wave is first[k].  Returns the number of packs written to out (at most
+// cap), or -1 if a width does not divide kWaves or the packs do not fit.
+template <class PackT, int kWaves>
+int pack_by_width(const std::vector<int>& widths, PackT* out, int cap) {
+  std::vector<std::vector<int>> by_w(kWaves + 1);
+  for (size_t i = 0; i < widths.size(); ++i) {
+    const int W = widths[i];
+    if (W < 1 || W > kWaves || kWaves % W) return -1;
+    by_w[W].push_back((int)i);
+  }
+  int np = 0;
+  for (int W = kWaves; W >= 1; --W) {
+    const std::vector<int>& v = by_w[W];
+    const int per = kWaves / W;
+    for (size_t i = 0; i < v.size(); i += per) {
+      if (np >= cap) return -1;
+      PackT& pk = out[np++];
+      for (int k = 0; k < kWaves; ++k) {
+        pk.inst[k] = -1;
+        pk.seg[k] = 0;
+        pk.first[k] = (int16_t)k;
+      }
+      for (int m = 0; m < per && i + m < v.size(); ++m)
+        for (int k = 0; k < W; ++k) {
+          pk.inst[m * W + k] = v[i + m];
+          pk.seg[m * W + k] = (int16_t)k;
+          pk.first[m * W + k] = (int16_t)(m * W);
+        }
+    }
+  }
+  return np;
+}
+
 struct SchedReq {
   uint64_t ticket = 0;
   size_t charge = 0;      // bytes counted against the budget
@@ -143,6 +185,8 @@ class Scheduler {
       for (auto* r : batch) r->t_launch = t;
       Launch L;
       L.reqs = batch;
+      L.fin.assign(batch.size(), 0);
+      L.reported.assign(batch.size(), 0);
       L.t_launch = t;
       L.handle = ex_->launch(batch);
       launches_.push_back(L);
@@ -161,40 +205,54 @@ class Scheduler {
  private:
   struct Launch {
     std::vector<SchedReq*> reqs;
+    std::vector<char> fin;        // request's memory released
+    std::vector<char> reported;   // request handed back (finished or timed out)
     typename Exec::Handle handle;
     double t_launch = 0;
     bool timed_out = false;
   };
 
+  // Executor contract: poll() fills st[k] with request k's status once it has
+  // finished (-1 while it runs) and returns true once the whole launch is
+  // over (every st[k] >= 0; its resources may then be released).
   void retire(std::vector<SchedReq*>& done) {
     for (size_t i = 0; i < launches_.size();) {
       Launch& L = launches_[i];
       std::vector<int> st;
-      if (ex_->poll(L.handle, L.reqs, st)) {
-        const double t = mono_now();
-        for (size_t k = 0; k < L.reqs.size(); ++k) {
-          SchedReq* r = L.reqs[k];
-          arena_.release(r->arena_off, r->ws_bytes);
-          charge_ -= r->charge;
-          inflight_reqs_--;
-          if (!L.timed_out) {
-            r->status = st[k];
-            r->t_done = t;
-            done.push_back(r);
-            stats_.completed++;
-          }
+      const bool over = ex_->poll(L.handle, L.reqs, st);
+      const double t = mono_now();
+      for (size_t k = 0; k < L.reqs.size(); ++k) {
+        if (L.fin[k]) continue;
+        int s = k < st.size() ? st[k] : -1;
+        if (s < 0 && over) s = 4;   // EDEVICE: launch over without a status
+        if (s < 0) continue;
+        SchedReq* r = L.reqs[k];
+        L.fin[k] = 1;
+        arena_.release(r->arena_off, r->ws_bytes);
+        charge_ -= r->charge;
+        inflight_reqs_--;
+        if (!L.reported[k]) {
+          L.reported[k] = 1;
+          r->status = s;
+          r->t_done = t;
+          done.push_back(r);
+          stats_.completed++;
         }
+      }
+      if (over) {
         ex_->release(L.handle);
         launches_.erase(launches_.begin() + i);
         continue;
       }
-      // watchdog: report a launch that never finishes; its memory stays
-      // reserved until the executor reports it done
-      if (!L.timed_out && watchdog_s_ > 0 && mono_now() - L.t_launch > watchdog_s_) {
+      // watchdog: report the requests of a launch that never finishes; their
+      // memory stays reserved until the executor reports them done
+      if (!L.timed_out && watchdog_s_ > 0 && t - L.t_launch > watchdog_s_) {
         L.timed_out = true;
         stats_.timeouts++;
-        const double t = mono_now();
-        for (SchedReq* r : L.reqs) {
+        for (size_t k = 0; k < L.reqs.size(); ++k) {
+          if (L.reported[k]) continue;
+          L.reported[k] = 1;
+          SchedReq* r = L.reqs[k];
           r->status = 4;   // EDEVICE
           r->t_done = t;
           done.push_back(r);

@@ -3,19 +3,27 @@
 // Requests (device-resident emissions and labels) are submitted from any host
 // thread; a worker thread runs the Scheduler (sched.hpp): strict FIFO
 // admission against the backpointer-memory budget, first-fit placement of
-// each admitted request's workspace in one device arena, and launch of the
-// admitted group.  A group's small alignments (S <= 4096) run as one
-// persistent pack kernel; each larger one gets its own single-instance launch.
-// Every launch uses a slot of its own (stream from a pool, pinned descriptor
-// buffers, status array, completion event), so groups admitted while others
-// are still running overlap on the device.  Completion is observed by
-// querying the slots' events; statuses come back through pinned memory.
+// each admitted request's workspace in one device arena, then the executor
+// below.
+//
+// The executor keeps one resident kernel on the device (k_serve: a 16-wave
+// workgroup per CU) instead of launching kernels per group: launches queued
+// behind a running kernel on a shared hardware queue would wait for it to
+// finish, so a short request could sit behind a long one.  The host turns
+// each admitted group into work items (small alignments packed 16 waves to
+// an item, each larger or padded one alone), keeps them in a FIFO and hands
+// them to idle workgroups through per-workgroup mailboxes in fine-grained
+// pinned host memory.  Each alignment raises its own completion flag there as
+// soon as its outputs are written, so a request is reported (and its memory
+// reused) without waiting for anything else.  The kernel is stopped after a
+// short idle period and started again when work arrives.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
 #include <condition_variable>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -30,168 +38,241 @@ using namespace ctca;
 
 namespace {
 
-constexpr int kSlots = 32;          // concurrent launches
-constexpr int kStreams = 8;         // stream pool (default priority)
-constexpr int kMaxBatch = 1024;     // requests per admitted group
+constexpr int kMaxBatch = 1024;       // requests per admitted group
+constexpr int kFlags = 1 << 16;       // completion flags (requests in flight)
+constexpr double kIdleStop = 0.02;    // seconds without work before the kernel is stopped
+constexpr int64_t kDeviceIdle = 1000000000;  // a workgroup's own idle limit: 10 s of the 100 MHz clock
 
 struct Payload {
   ctcalign_request req;
   Geo g;
-  bool pack;        // runs in the persistent pack kernel
   size_t bp_bytes;  // workspace part for backpointers
   size_t pad_bytes; // workspace part for a padded emission copy (0 if none)
   int stride;
 };
 
-struct Slot {
-  bool busy = false;
-  hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;
-  Inst* h_inst = nullptr;       // pinned
-  Pack* h_pack = nullptr;       // pinned
-  int32_t* h_status = nullptr;  // pinned
-  int32_t* h_order = nullptr;   // pinned
-  Inst* d_inst = nullptr;
-  int32_t* d_order = nullptr;
-  Pack* d_pack = nullptr;
-  int32_t* d_status = nullptr;
-  int* d_head = nullptr;
-  int n = 0;
+// 16-wave pack of small alignments (pack_by_width's layout)
+struct Pack16 {
+  int32_t inst[kServeWaves];
+  int16_t seg[kServeWaves];
+  int16_t first[kServeWaves];
 };
 
-class HipExec {
+template <class T>
+int host_alloc(T** h, T** d, size_t n) {
+  HIP_TRY(hipHostMalloc((void**)h, sizeof(T) * n, hipHostMallocMapped | hipHostMallocCoherent));
+  std::memset((void*)*h, 0, sizeof(T) * n);
+  HIP_TRY(hipHostGetDevicePointer((void**)d, *h, 0));
+  return CTCALIGN_OK;
+}
+
+class ServeExec {
  public:
   struct Handle {
-    std::vector<int> slots;
-    std::vector<std::pair<int, int>> where;   // per request: (slot, index in slot)
+    std::vector<int> flag;   // per request: its completion flag
   };
 
-  HipExec(ctcalign_ctx* ctx, char* arena) : ctx_(ctx), arena_(arena) {}
+  ServeExec(ctcalign_ctx* ctx, char* arena) : ctx_(ctx), arena_(arena) {}
 
   int init() {
-    for (int i = 0; i < kStreams; ++i) HIP_TRY(hipStreamCreateWithFlags(&streams_[i], hipStreamNonBlocking));
-    for (int i = 0; i < kSlots; ++i) {
-      Slot& s = slots_[i];
-      s.stream = streams_[i % kStreams];
-      HIP_TRY(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
-      HIP_TRY(hipHostMalloc((void**)&s.h_inst, sizeof(Inst) * kMaxBatch));
-      HIP_TRY(hipHostMalloc((void**)&s.h_pack, sizeof(Pack) * kMaxBatch));
-      HIP_TRY(hipHostMalloc((void**)&s.h_status, sizeof(int32_t) * kMaxBatch));
-      HIP_TRY(hipHostMalloc((void**)&s.h_order, sizeof(int32_t) * kMaxBatch));
-      HIP_TRY(hipMalloc((void**)&s.d_order, sizeof(int32_t) * kMaxBatch));
-      HIP_TRY(hipMalloc((void**)&s.d_inst, sizeof(Inst) * kMaxBatch));
-      HIP_TRY(hipMalloc((void**)&s.d_pack, sizeof(Pack) * kMaxBatch));
-      HIP_TRY(hipMalloc((void**)&s.d_status, sizeof(int32_t) * kMaxBatch));
-      HIP_TRY(hipMalloc((void**)&s.d_head, sizeof(int)));
-    }
+    grid_ = std::max(ctx_->num_cu, 1);
+    HIP_TRY(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&ended_, hipEventDisableTiming));
+    int rc;
+    if ((rc = host_alloc(&h_items_, &d_items_, grid_)) || (rc = host_alloc(&h_box_, &d_box_, grid_)) ||
+        (rc = host_alloc(&h_stop_, &d_stop_, 16)) || (rc = host_alloc(&h_flag_, &d_flag_, kFlags)))
+      return rc;
+    sent_.assign(grid_, 0);
+    free_flag_.reserve(kFlags);
+    for (int i = kFlags - 1; i >= 0; --i) free_flag_.push_back(i);
     return CTCALIGN_OK;
   }
 
+  // stops the kernel (finishing the items it runs) and frees everything
   void destroy() {
-    for (auto& st : streams_)
-      if (st) (void)hipStreamSynchronize(st);
-    for (auto& s : slots_) {
-      if (s.done) (void)hipEventDestroy(s.done);
-      if (s.h_inst) (void)hipHostFree(s.h_inst);
-      if (s.h_pack) (void)hipHostFree(s.h_pack);
-      if (s.h_status) (void)hipHostFree(s.h_status);
-      if (s.h_order) (void)hipHostFree(s.h_order);
-      if (s.d_order) (void)hipFree(s.d_order);
-      if (s.d_inst) (void)hipFree(s.d_inst);
-      if (s.d_pack) (void)hipFree(s.d_pack);
-      if (s.d_status) (void)hipFree(s.d_status);
-      if (s.d_head) (void)hipFree(s.d_head);
-      s = Slot();
-    }
-    for (auto& st : streams_)
-      if (st) (void)hipStreamDestroy(st);
+    if (h_stop_) __atomic_store_n(h_stop_, 1, __ATOMIC_RELEASE);
+    if (stream_) (void)hipStreamSynchronize(stream_);
+    if (ended_) (void)hipEventDestroy(ended_);
+    if (stream_) (void)hipStreamDestroy(stream_);
+    for (void* h : {(void*)h_items_, (void*)h_box_, (void*)h_stop_, (void*)h_flag_})
+      if (h) (void)hipHostFree(h);
+    h_items_ = nullptr;
+    h_box_ = nullptr;
+    h_stop_ = nullptr;
+    h_flag_ = nullptr;
+    stream_ = nullptr;
+    ended_ = nullptr;
   }
 
   int max_batch() const { return kMaxBatch; }
 
-  // a group needs up to (#large + 1) slots; keep a margin of half the pool
+  // room for a whole group: its flags, and a bounded FIFO of items
   bool can_launch() const {
-    int free = 0;
-    for (auto& s : slots_) free += !s.busy;
-    return free > kSlots / 2;
+    return (int)free_flag_.size() >= kMaxBatch && (int)pending_.size() < 4 * grid_;
   }
 
   Handle launch(std::vector<SchedReq*>& reqs) {
     Handle h;
-    h.where.resize(reqs.size());
-    int small_slot = -1, long_slot = -1;
-    int nsmall = 0, nlong = 0;
+    h.flag.resize(reqs.size());
+    std::vector<Inst> insts(reqs.size());
+    std::vector<int> small;
     for (size_t k = 0; k < reqs.size(); ++k) {
       const Payload* p = static_cast<Payload*>(reqs[k]->user);
-      if (p->pack) {
-        if (small_slot < 0) small_slot = take_slot();
-        h.where[k] = {small_slot, nsmall};
-        slots_[small_slot].h_inst[nsmall] = make_inst(*p, reqs[k]->arena_off, slots_[small_slot].d_status + nsmall);
-        ++nsmall;
-      } else if (!p->pad_bytes) {
-        // large trellis: all of this group's go to one persistent launch
-        if (long_slot < 0) long_slot = take_slot();
-        h.where[k] = {long_slot, nlong};
-        slots_[long_slot].h_inst[nlong] = make_inst(*p, reqs[k]->arena_off, slots_[long_slot].d_status + nlong);
-        ++nlong;
+      const int f = free_flag_.back();
+      free_flag_.pop_back();
+      __atomic_store_n(h_flag_ + f, -1, __ATOMIC_RELEASE);
+      h.flag[k] = f;
+      insts[k] = make_inst(*p, reqs[k]->arena_off, d_flag_ + f);
+      if (p->pad_bytes || p->g.W > kPackWaves) {
+        ServeItem it = blank_item();
+        it.inst[0] = insts[k];
+        for (int w = 0; w < p->g.W; ++w) {
+          it.which[w] = 0;
+          it.seg[w] = (int8_t)w;
+          it.first[w] = 0;
+        }
+        if (p->pad_bytes) {
+          it.npad = 1;
+          it.pad = PadDesc{p->req.emission, const_cast<float*>(insts[k].em), p->req.T, p->req.C,
+                           p->stride, 0};
+        }
+        pending_.push_back(it);
       } else {
-        const int sl = take_slot();
-        Slot& s = slots_[sl];
-        s.h_inst[0] = make_inst(*p, reqs[k]->arena_off, s.d_status);
-        s.n = 1;
-        h.where[k] = {sl, 0};
-        h.slots.push_back(sl);
-        submit_one(s, *p, reqs[k]->arena_off);
+        small.push_back((int)k);
       }
     }
-    if (long_slot >= 0) {
-      Slot& s = slots_[long_slot];
-      s.n = nlong;
-      h.slots.push_back(long_slot);
-      submit_long(s);
+    if (!small.empty()) {
+      // similar chain lengths share an item (an item holds its workgroup
+      // until its longest alignment is done)
+      std::sort(small.begin(), small.end(), [&](int a, int b) {
+        return (int64_t)insts[a].T * insts[a].M > (int64_t)insts[b].T * insts[b].M;
+      });
+      std::vector<int> widths(small.size());
+      for (size_t i = 0; i < small.size(); ++i) widths[i] = insts[small[i]].W;
+      std::vector<Pack16> packs(small.size());
+      const int np = pack_by_width<Pack16, kServeWaves>(widths, packs.data(), (int)packs.size());
+      for (int q = 0; q < np; ++q) {
+        ServeItem it = blank_item();
+        int used = 0;
+        int slot_of[kServeWaves];
+        for (int w = 0; w < kServeWaves; ++w) {
+          const int i = packs[q].inst[w];
+          if (i < 0) continue;
+          if (packs[q].seg[w] == 0) {
+            slot_of[w] = used;
+            it.inst[used++] = insts[small[i]];
+          } else {
+            slot_of[w] = slot_of[packs[q].first[w]];
+          }
+          it.which[w] = (int8_t)slot_of[w];
+          it.seg[w] = (int8_t)packs[q].seg[w];
+          it.first[w] = (int8_t)packs[q].first[w];
+        }
+        pending_.push_back(it);
+      }
     }
-    if (small_slot >= 0) {
-      Slot& s = slots_[small_slot];
-      s.n = nsmall;
-      h.slots.push_back(small_slot);
-      submit_packs(s);
-    }
+    pump();
     return h;
   }
 
+  // st[k]: request k's status once its flag is up, else -1 (EDEVICE for
+  // all once the kernel could not be launched)
   bool poll(Handle& h, const std::vector<SchedReq*>& reqs, std::vector<int>& st) {
-    for (int sl : h.slots)
-      if (hipEventQuery(slots_[sl].done) == hipErrorNotReady) return false;
-    st.resize(reqs.size());
+    st.assign(reqs.size(), -1);
+    bool all = true;
     for (size_t k = 0; k < reqs.size(); ++k) {
-      const int sl = h.where[k].first;
-      st[k] = launch_err_[sl] ? CTCALIGN_EDEVICE : slots_[sl].h_status[h.where[k].second];
+      st[k] = __atomic_load_n(h_flag_ + h.flag[k], __ATOMIC_ACQUIRE);
+      if (st[k] < 0 && launch_failed_ && !running_) st[k] = CTCALIGN_EDEVICE;
+      all &= st[k] >= 0;
     }
-    return true;
+    return all;
   }
 
   void release(Handle& h) {
-    for (int sl : h.slots) {
-      slots_[sl].busy = false;
-      launch_err_[sl] = false;
-    }
-    h.slots.clear();
+    for (int f : h.flag) free_flag_.push_back(f);
+    h.flag.clear();
   }
 
- private:
-  int take_slot() {
-    for (int i = 0; i < kSlots; ++i) {
-      const int sl = (next_ + i) % kSlots;
-      if (!slots_[sl].busy) {
-        slots_[sl].busy = true;
-        next_ = sl + 1;
-        return sl;
+  // Starts or stops the kernel and hands queued items to idle workgroups.
+  // Called by the worker after every scheduling round.
+  void pump() {
+    if (running_ && hipEventQuery(ended_) != hipErrorNotReady) {
+      running_ = false;
+      if (stopping_) {
+        stopping_ = false;
+        __atomic_store_n(h_stop_, 0, __ATOMIC_RELEASE);
       }
     }
-    return 0;   // unreachable: can_launch() keeps half the pool free
+    const bool unacked = any_unacked();
+    if (!running_ && !launch_failed_ && (!pending_.empty() || unacked)) {
+      ++epoch_;
+      // workgroups of an earlier launch that never got to run their mailbox
+      // find it again: a new launch starts from the last acknowledged item
+      const bool err = launch_serve(d_items_, d_box_, d_stop_, epoch_, kDeviceIdle, grid_, stream_) !=
+                           hipSuccess ||
+                       hipEventRecord(ended_, stream_) != hipSuccess;
+      if (err) {
+        // the device no longer runs kernels: every queued and future
+        // request fails (nothing of theirs can still be running)
+        launch_failed_ = true;
+        pending_.clear();
+        return;
+      }
+      running_ = true;
+      last_work_ = mono_now();
+    }
+    if (!running_ || stopping_) return;
+    for (int n = 0; n < grid_ && !pending_.empty(); ++n) {
+      const int b = rr_;
+      rr_ = (rr_ + 1) % grid_;
+      const uint64_t live = __atomic_load_n(&h_box_[b].live, __ATOMIC_ACQUIRE);
+      const uint64_t ack = __atomic_load_n(&h_box_[b].ack, __ATOMIC_ACQUIRE);
+      if (live != epoch_ || ack != sent_[b]) continue;
+      std::memcpy((void*)&h_items_[b], &pending_.front(), sizeof(ServeItem));
+      pending_.pop_front();
+      ++sent_[b];
+      __atomic_store_n(&h_box_[b].mail, sent_[b] << 32, __ATOMIC_RELEASE);
+      // a workgroup leaving withdraws `live` before its last look at the
+      // mailbox: if it is gone now, it may not have seen this item, and a
+      // restarted kernel runs it
+      __atomic_thread_fence(__ATOMIC_SEQ_CST);
+      if (__atomic_load_n(&h_box_[b].live, __ATOMIC_ACQUIRE) != epoch_) {
+        stopping_ = true;
+        __atomic_store_n(h_stop_, 1, __ATOMIC_RELEASE);
+        break;
+      }
+    }
+    if (!pending_.empty() || unacked) {
+      last_work_ = mono_now();
+    } else if (mono_now() - last_work_ > kIdleStop) {
+      stopping_ = true;
+      __atomic_store_n(h_stop_, 1, __ATOMIC_RELEASE);
+    }
   }
 
-  Inst make_inst(const Payload& p, size_t off, int32_t* status) {
+  // nothing queued or running on the device
+  bool device_idle() const { return !running_ && pending_.empty(); }
+  bool launch_failed() const { return launch_failed_; }
+
+ private:
+  bool any_unacked() const {
+    for (int b = 0; b < grid_; ++b)
+      if (__atomic_load_n(&h_box_[b].ack, __ATOMIC_ACQUIRE) != sent_[b]) return true;
+    return false;
+  }
+
+  static ServeItem blank_item() {
+    ServeItem it;
+    std::memset(&it, 0, sizeof(it));
+    for (int w = 0; w < kServeWaves; ++w) {
+      it.which[w] = -1;
+      it.seg[w] = 0;
+      it.first[w] = (int8_t)w;
+    }
+    return it;
+  }
+
+  Inst make_inst(const Payload& p, size_t off, int32_t* notify) {
     Inst in{};
     in.T = p.req.T;
     in.C = p.req.C;
@@ -201,7 +282,8 @@ class HipExec {
     in.path = p.req.out_path;
     in.scores = p.req.out_scores;
     in.total = p.req.out_total;
-    in.status = status;
+    in.status = nullptr;
+    in.notify = notify;
     in.W = p.g.W;
     in.M = p.g.M;
     in.stride = p.stride;
@@ -211,89 +293,22 @@ class HipExec {
     return in;
   }
 
-  void pad_if_needed(const Payload& p, size_t off, hipStream_t st, bool& err) {
-    if (!p.pad_bytes) return;
-    const PadDesc pd{p.req.emission, reinterpret_cast<float*>(arena_ + off + p.bp_bytes), p.req.T,
-                     p.req.C, p.stride, 0};
-    err |= launch_pad_one(pd, st) != hipSuccess;
-  }
-
-  void submit_one(Slot& s, const Payload& p, size_t off) {
-    const int sl = (int)(&s - slots_);
-    bool err = false;
-    pad_if_needed(p, off, s.stream, err);
-    err |= launch_one(s.h_inst[0], s.stream) != hipSuccess;
-    err |= hipMemcpyAsync(s.h_status, s.d_status, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream) != hipSuccess;
-    err |= hipEventRecord(s.done, s.stream) != hipSuccess;
-    launch_err_[sl] = err;
-  }
-
-  void submit_long(Slot& s) {
-    const int sl = (int)(&s - slots_);
-    bool err = false;
-    // longest first
-    for (int i = 0; i < s.n; ++i) s.h_order[i] = i;
-    std::sort(s.h_order, s.h_order + s.n, [&](int a, int b) {
-      return (int64_t)s.h_inst[a].T * s.h_inst[a].M > (int64_t)s.h_inst[b].T * s.h_inst[b].M;
-    });
-    err |= hipMemcpyAsync(s.d_inst, s.h_inst, sizeof(Inst) * s.n, hipMemcpyHostToDevice, s.stream) != hipSuccess;
-    err |= hipMemcpyAsync(s.d_order, s.h_order, sizeof(int32_t) * s.n, hipMemcpyHostToDevice, s.stream) != hipSuccess;
-    err |= launch_fill(s.d_head, 1, 0, s.stream) != hipSuccess;
-    const int grid = std::min(s.n, ctx_->num_cu * 4);
-    err |= launch_persistent_long(s.d_inst, s.d_order, s.n, s.d_head, grid, s.stream) != hipSuccess;
-    err |= hipMemcpyAsync(s.h_status, s.d_status, sizeof(int32_t) * s.n, hipMemcpyDeviceToHost, s.stream) != hipSuccess;
-    err |= hipEventRecord(s.done, s.stream) != hipSuccess;
-    launch_err_[sl] = err;
-  }
-
-  void submit_packs(Slot& s) {
-    const int sl = (int)(&s - slots_);
-    bool err = false;
-    // packs of kPackWaves waves: kPackWaves / W instances of W waves each
-    // (padded emissions never come here: they take a single launch with its
-    // pad kernel)
-    std::vector<int> by_w[kPackWaves + 1];
-    for (int i = 0; i < s.n; ++i) by_w[s.h_inst[i].W].push_back(i);
-    int np = 0;
-    auto blank_pack = [] {
-      Pack pk;
-      for (int k = 0; k < kPackWaves; ++k) {
-        pk.inst[k] = -1;
-        pk.seg[k] = 0;
-        pk.first[k] = (int16_t)k;
-      }
-      return pk;
-    };
-    for (int W : {8, 4, 2, 1}) {
-      const auto& v = by_w[W];
-      const int per = kPackWaves / W;
-      for (size_t i = 0; i < v.size(); i += per) {
-        Pack pk = blank_pack();
-        for (int m = 0; m < per && i + m < v.size(); ++m)
-          for (int k = 0; k < W; ++k) {
-            pk.inst[m * W + k] = v[i + m];
-            pk.seg[m * W + k] = (int16_t)k;
-            pk.first[m * W + k] = (int16_t)(m * W);
-          }
-        s.h_pack[np++] = pk;
-      }
-    }
-    err |= hipMemcpyAsync(s.d_inst, s.h_inst, sizeof(Inst) * s.n, hipMemcpyHostToDevice, s.stream) != hipSuccess;
-    err |= hipMemcpyAsync(s.d_pack, s.h_pack, sizeof(Pack) * np, hipMemcpyHostToDevice, s.stream) != hipSuccess;
-    err |= launch_fill(s.d_head, 1, 0, s.stream) != hipSuccess;
-    const int grid = std::min(np, ctx_->num_cu * 16);
-    err |= launch_persistent(s.d_inst, s.d_pack, np, s.d_head, grid, s.stream, nullptr) != hipSuccess;
-    err |= hipMemcpyAsync(s.h_status, s.d_status, sizeof(int32_t) * s.n, hipMemcpyDeviceToHost, s.stream) != hipSuccess;
-    err |= hipEventRecord(s.done, s.stream) != hipSuccess;
-    launch_err_[sl] = err;
-  }
-
   ctcalign_ctx* ctx_;
   char* arena_;
-  hipStream_t streams_[kStreams] = {};
-  Slot slots_[kSlots];
-  bool launch_err_[kSlots] = {};
-  int next_ = 0;
+  int grid_ = 0;
+  hipStream_t stream_ = nullptr;
+  hipEvent_t ended_ = nullptr;
+  ServeItem *h_items_ = nullptr, *d_items_ = nullptr;
+  ServeBox *h_box_ = nullptr, *d_box_ = nullptr;
+  int32_t *h_stop_ = nullptr, *d_stop_ = nullptr;
+  int32_t *h_flag_ = nullptr, *d_flag_ = nullptr;
+  std::vector<uint64_t> sent_;       // per workgroup: sequence of the last item posted
+  std::vector<int> free_flag_;
+  std::deque<ServeItem> pending_;    // items waiting for an idle workgroup
+  uint64_t epoch_ = 0;
+  int rr_ = 0;
+  bool running_ = false, stopping_ = false, launch_failed_ = false;
+  double last_work_ = 0;
 };
 
 }  // namespace
@@ -303,8 +318,8 @@ struct ctcalign_server {
   void* arena = nullptr;
   size_t arena_bytes = 0;
   size_t budget = 0;
-  HipExec* exec = nullptr;
-  Scheduler<HipExec>* sched = nullptr;
+  ServeExec* exec = nullptr;
+  Scheduler<ServeExec>* sched = nullptr;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::thread worker;
@@ -323,14 +338,18 @@ void worker_loop(ctcalign_server* s) {
   for (;;) {
     if (s->stop && s->sched->idle()) break;
     std::vector<SchedReq*> done = s->sched->step();
+    s->exec->pump();
     if (!done.empty()) {
       s->completed += done.size();
       s->cv_done.notify_all();
     }
-    if (s->sched->idle()) {
+    if (s->sched->idle() && s->exec->device_idle()) {
       s->cv_work.wait_for(lk, std::chrono::milliseconds(50));
+    } else if (s->sched->idle()) {
+      // the kernel idles on the device: look again before stopping it
+      s->cv_work.wait_for(lk, std::chrono::milliseconds(1));
     } else {
-      // launches in flight: poll their events every few microseconds
+      // requests in flight: poll their flags every few microseconds
       lk.unlock();
       std::this_thread::sleep_for(std::chrono::microseconds(10));
       lk.lock();
@@ -367,7 +386,7 @@ int ctcalign_server_create(ctcalign_ctx* ctx, size_t bp_budget_bytes, int32_t ma
     delete s;
     return rc;
   }
-  s->exec = new HipExec(ctx, static_cast<char*>(s->arena));
+  s->exec = new ServeExec(ctx, static_cast<char*>(s->arena));
   rc = s->exec->init();
   if (rc) {
     s->exec->destroy();
@@ -376,7 +395,7 @@ int ctcalign_server_create(ctcalign_ctx* ctx, size_t bp_budget_bytes, int32_t ma
     delete s;
     return rc;
   }
-  s->sched = new Scheduler<HipExec>(s->exec, bp_budget_bytes, s->arena_bytes, max_inflight, 30.0);
+  s->sched = new Scheduler<ServeExec>(s->exec, bp_budget_bytes, s->arena_bytes, max_inflight, 30.0);
   s->worker = std::thread(worker_loop, s);
   *out = s;
   return CTCALIGN_OK;
@@ -386,21 +405,15 @@ int ctcalign_server_submit(ctcalign_server* s, const ctcalign_request* r, uint64
   if (!s || !r || !ticket) return CTCALIGN_EINVAL;
   if (!r->emission || !r->out_path || !r->out_scores || r->T < 1 || r->T > (1 << 30) || r->C < 1 ||
       r->C > kMaxC || r->L < 0 || (r->L > 0 && !r->labels) || r->blank < 0 || r->blank >= r->C ||
-      2 * (int64_t)r->L + 1 > kMaxS)
+      2 * (int64_t)r->L + 1 > s->ctx->tune.max_serve_states())
     return CTCALIGN_EINVAL;
   Payload* p = new (std::nothrow) Payload();
   if (!p) return CTCALIGN_ENOMEM;
   p->req = *r;
   const int S = 2 * r->L + 1;
   p->stride = row_stride_for(r->C);
-  if (S <= s->ctx->tune.max_pack_states()) {
-    p->g = s->ctx->tune.pick_pack(S, r->C, r->T);
-    p->pack = true;
-  } else {
-    p->g = s->ctx->tune.pick_long(S);
-    p->pack = false;
-  }
-  if (p->g.W == 0 || !geo_ok(S, p->g.W, p->g.M)) {
+  p->g = s->ctx->tune.pick_serve(S, r->C, r->T);
+  if (p->g.W == 0 || !geo_ok_top1(S, p->g.W, p->g.M) || !geometry_supported_serve(p->g.W, p->g.M)) {
     delete p;
     return CTCALIGN_EINVAL;
   }
@@ -408,12 +421,6 @@ int ctcalign_server_submit(ctcalign_server* s, const ctcalign_request* r, uint64
   p->pad_bytes = (r->C != p->stride || !aligned16(r->emission))
                      ? round_up((size_t)r->T * p->stride * sizeof(float), 256)
                      : 0;
-  if (p->pad_bytes && p->pack) {
-    // padded emissions go through a single launch (its pad kernel runs on the same stream)
-    p->pack = false;
-    p->g = s->ctx->tune.pick_long(S);
-    p->bp_bytes = round_up((size_t)bp_words(r->T, p->g.W, p->g.M) * 4, 256);
-  }
   SchedReq* q = new (std::nothrow) SchedReq();
   if (!q) {
     delete p;

@@ -29,6 +29,12 @@ inline bool geo_ok(int S, int W, int M) {
   const int64_t seg = (int64_t)kWave * M;
   return (int64_t)W * seg >= S && ((int64_t)(W - 1) * seg + 2 <= S || W == 1);
 }
+// Layouts of single-workgroup kernels may also end on a segment that holds
+// S-1 alone: the end-state choice then takes a(S-2) from the boundary ring.
+inline bool geo_ok_top1(int S, int W, int M) {
+  const int64_t seg = (int64_t)kWave * M;
+  return (int64_t)W * seg >= S && ((int64_t)(W - 1) * seg + 1 <= S || W == 1);
+}
 
 struct TuneTable {
   int num_cu = 256;
@@ -110,6 +116,20 @@ struct TuneTable {
         if (W <= kPackWaves && geo_ok(S, W, M) && (best.W == 0 || M < best.M)) best = Geo{W, M};
     return best;
   }
+
+  // Serving: S up to the pack limit as in the batched kernel; larger ones
+  // take one resident 16-wave workgroup, with the fewest states per lane
+  // (from 8) that cover S.
+  Geo pick_serve(int S, int C, int T) const {
+    if (S <= max_pack_states()) return pick_pack(S, C, T);
+    for (int M : kMenuPack) {
+      if (M < 8) continue;
+      const int W = (S + kWave * M - 1) / (kWave * M);
+      if (W <= kServeWaves && geo_ok_top1(S, W, M)) return Geo{W, M};
+    }
+    return Geo{0, 0};
+  }
+  int64_t max_serve_states() const { return (int64_t)kServeWaves * kWave * 16; }
 
   // Largest trellis for the pack kernel: every S up to 4 * 64 * 16 has a
   // pack layout (W <= 4 covers them all; W = 8 layouts leave gaps above).

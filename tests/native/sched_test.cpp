@@ -23,12 +23,13 @@ static int failures = 0;
     }                                                                   \
   } while (0)
 
-// Completes each launch after `lag` polls; a launch containing a request
-// with `stuck` set never completes.  Tracks the charge on the "device".
+// Completes request k of a launch after lag + ticket % 3 polls (requests of
+// one launch finish at different times); a request with `user` set never
+// completes, nor does its launch.  Tracks the charge on the "device".
 struct FakeExec {
   struct Handle {
     int polls = 0;
-    bool stuck = false;
+    std::vector<char> stuck, fin;
   };
   int lag = 3;
   int cap = 64;
@@ -43,7 +44,8 @@ struct FakeExec {
     for (auto* r : reqs) {
       admit_order.push_back(r->ticket);
       device_charge += r->charge;
-      if (r->user) h.stuck = true;
+      h.stuck.push_back(r->user != nullptr);
+      h.fin.push_back(0);
     }
     peak = std::max(peak, device_charge);
     if (device_charge > budget) violated = true;
@@ -51,10 +53,19 @@ struct FakeExec {
     return h;
   }
   bool poll(Handle& h, const std::vector<SchedReq*>& reqs, std::vector<int>& st) {
-    if (h.stuck || ++h.polls < lag) return false;
-    st.assign(reqs.size(), 0);
-    for (auto* r : reqs) device_charge -= r->charge;
-    return true;
+    ++h.polls;
+    st.assign(reqs.size(), -1);
+    bool all = true;
+    for (size_t k = 0; k < reqs.size(); ++k) {
+      if (!h.stuck[k] && h.polls >= lag + (int)(reqs[k]->ticket % 3)) {
+        if (!h.fin[k]) device_charge -= reqs[k]->charge;
+        h.fin[k] = 1;
+        st[k] = 0;
+      } else {
+        all = false;
+      }
+    }
+    return all;
   }
   void release(Handle&) { --launches_open; }
 };
@@ -167,6 +178,93 @@ static void test_watchdog() {
   CHECK(s.charge_inflight() == 10);         // the hung launch keeps its memory
 }
 
+// A request that finishes before the rest of its launch is reported at
+// once and frees its charge, so the next request in line is admitted while
+// that launch is still open; the request that never finishes is reported by
+// the watchdog and keeps its memory.
+static void test_early_completion() {
+  FakeExec ex;
+  ex.budget = 100;
+  ex.cap = 2;
+  ex.lag = 1;
+  Scheduler<FakeExec> s(&ex, 100, 1 << 16, 10, 0.2);
+  std::vector<SchedReq> r(3);
+  int tag = 1;
+  const size_t charge[3] = {50, 40, 50};
+  for (int i = 0; i < 3; ++i) {
+    r[i].ticket = 3 * (i + 1);       // ticket % 3 == 0: done after `lag` polls
+    r[i].charge = charge[i];
+    r[i].ws_bytes = 256;
+    r[i].user = (i == 1) ? &tag : nullptr;   // request 2 never finishes
+    CHECK(s.submit(&r[i], 16) == 0);
+  }
+  s.step();
+  CHECK(s.inflight() == 2);        // 1 and 2 launched together; 3 does not fit
+  CHECK(s.waiting() == 1);
+  std::vector<SchedReq*> fin;
+  auto f = s.step();               // 1 finishes; 3 is admitted in the same round
+  fin.insert(fin.end(), f.begin(), f.end());
+  CHECK(fin.size() == 1 && fin[0] == &r[0] && r[0].status == 0);
+  CHECK(s.waiting() == 0);
+  CHECK(s.charge_inflight() == 90);
+  const double t0 = mono_now();
+  while (fin.size() < 3 && mono_now() - t0 < 2.0) {
+    f = s.step();
+    fin.insert(fin.end(), f.begin(), f.end());
+    std::this_thread::sleep_for(std::chrono::milliseconds(1));
+  }
+  CHECK(fin.size() == 3);
+  CHECK(r[2].status == 0);
+  CHECK(r[1].status == 4);         // EDEVICE from the watchdog
+  CHECK(s.stats().timeouts == 1);
+  CHECK(s.charge_inflight() == 40);
+  CHECK(s.stats().completed == 3);
+}
+
+// Pack construction of the server: every alignment gets exactly its W waves,
+// consecutive, segments 0..W-1 in order, `first` pointing at its first wave;
+// packs are full except the last of each width; bad widths and overflow are
+// refused.  (A loop over a width the pack could not hold once read past the
+// end of an array here.)
+struct TestPack {
+  int32_t inst[4];
+  int16_t seg[4];
+  int16_t first[4];
+};
+
+static void test_pack_by_width() {
+  std::mt19937_64 rng(11);
+  for (int trial = 0; trial < 200; ++trial) {
+    const int n = (int)(rng() % 40);
+    std::vector<int> widths(n);
+    int cnt[5] = {};
+    for (auto& w : widths) {
+      w = 1 << (rng() % 3);
+      cnt[w]++;
+    }
+    std::vector<TestPack> out(64);
+    const int np = pack_by_width<TestPack, 4>(widths, out.data(), (int)out.size());
+    CHECK(np == (cnt[4] + (cnt[2] + 1) / 2 + (cnt[1] + 3) / 4));
+    std::vector<int> seen(n, 0);
+    for (int p = 0; p < np; ++p) {
+      for (int k = 0; k < 4; ++k) {
+        const int i = out[p].inst[k];
+        if (i < 0) continue;
+        CHECK(i < n);
+        const int W = widths[i], f = out[p].first[k];
+        CHECK(out[p].seg[k] == k - f);
+        CHECK(f % W == 0 && k - f < W && f + W <= 4);
+        seen[i]++;
+      }
+    }
+    for (int i = 0; i < n; ++i) CHECK(seen[i] == widths[i]);
+  }
+  TestPack few[2];
+  CHECK((pack_by_width<TestPack, 4>({4, 4, 4}, few, 2)) == -1);   // does not fit
+  CHECK((pack_by_width<TestPack, 4>({3}, few, 2)) == -1);         // 3 does not divide 4
+  CHECK((pack_by_width<TestPack, 4>({8}, few, 2)) == -1);         // wider than a pack
+}
+
 static void test_arena() {
   std::mt19937_64 rng(3);
   ArenaMap a(1 << 20);
@@ -196,6 +294,8 @@ int main() {
   test_refusals();
   test_max_inflight_and_no_overtake();
   test_watchdog();
+  test_early_completion();
+  test_pack_by_width();
   test_arena();
   if (failures) {
     std::fprintf(stderr, "%d check(s) failed\n", failures);

@@ -43,3 +43,24 @@ def test_multi_menu_covers_long_single_launches():
     gaps = [S for S in range(4097, 32769, 2)
             if not any(geo_ok(S, -(-S // (64 * M)), M) and -(-S // (64 * M)) <= 256 for M in multi)]
     assert gaps == []
+
+
+def test_serve_menu_covers_large_requests():
+    # the resident serving kernel runs trellises above the pack limit on one
+    # 16-wave workgroup: the chooser takes the first M >= 8 of the pack menu
+    # with W = ceil(S / (64 M)) <= 16 whose top wave holds S-1 (and S-2, or
+    # else takes a(S-2) from the boundary ring); every odd S up to
+    # 16 * 64 * 16 must find one
+    pack = [m for m in menu("kMenuPack") if m >= 8]
+
+    def top1_ok(S, W, M):
+        seg = 64 * M
+        return W * seg >= S and (W == 1 or (W - 1) * seg + 1 <= S)
+
+    gaps = [S for S in range(4097, 16385, 2)
+            if not any(top1_ok(S, -(-S // (64 * M)), M) and -(-S // (64 * M)) <= 16 for M in pack)]
+    assert gaps == []
+    # without the one-state top segment two sizes would have no layout
+    strict = [S for S in range(4097, 16385, 2)
+              if not any(geo_ok(S, -(-S // (64 * M)), M) and -(-S // (64 * M)) <= 16 for M in pack)]
+    assert strict == [14337, 15361]

@@ -93,6 +93,7 @@ def test_server_tiny_budget_serialises_but_matches():
 
 def test_server_alone_equals_mixed():
     import paper_2310_17864_amd as ca
+    torch, _ = torch_dev()
     utts = _pool()[:12]
     bufs = _upload(utts)
     _serve(utts, bufs, 64 << 30)
@@ -100,6 +101,7 @@ def test_server_alone_equals_mixed():
     srv = ca.Server(64 << 30)
     for u, b, (p, s) in zip(utts, bufs, mixed):
         b["path"].fill_(-7)
+        torch.cuda.synchronize()          # requests must not race the caller's own writes
         t = srv.submit(b["em"], b["lab"], b["path"], b["sc"], b["tot"], u.blank)
         srv.wait(t)
         assert np.array_equal(b["path"].cpu().numpy(), p)
@@ -117,3 +119,34 @@ def test_server_refuses_oversize():
         srv.submit(b["em"], b["lab"], b["path"], b["sc"], b["tot"])
     assert ei.value.code == ca.ENOMEM
     srv.close()
+
+
+def test_server_top_segment_single_state():
+    # trellis sizes S = 64*M*k + 1: the served layout's top wave holds S-1
+    # alone and takes a(S-2) from the boundary ring of the wave below; paths
+    # ending in S-2 and in S-1, a one-frame request, and the two sizes
+    # (S = 14337, 15361) no layout with two states on top covers
+    import paper_2310_17864_amd as ca
+    torch, dev = torch_dev()
+    utts = []
+    for T, L in ((12000, 2304), (30000, 7168), (30000, 7680)):
+        ends = set()
+        for seed in range(40):
+            u = synth.utterance(np.random.default_rng(seed), T, 32, L, 0, 6.0, 1.0, None)
+            end = int(u.planted[-1]) == 2 * L     # planted path ends in S-1 (blank)
+            if end not in ends:
+                ends.add(end)
+                utts.append(u)
+            if len(ends) == 2 or T > 12000:
+                break
+    utts.append(synth.Utterance(np.zeros((1, 32), np.float32),
+                                np.arange(1, 2305, dtype=np.int32) % 31 + 1, 0))
+    bufs = _upload(utts)
+    srv = ca.Server(64 << 30)
+    res = [srv.wait(srv.submit(b["em"], b["lab"], b["path"], b["sc"], b["tot"], u.blank))
+           for u, b in zip(utts, bufs)]
+    srv.close()
+    assert _check(utts, bufs, res) == []
+    ends = {int(np.asarray(p)[-1]) != 0 for p in (b["path"].cpu().numpy() for b in bufs[:2])}
+    assert ends == {True, False}                  # both end states taken
+    assert res[-1][0] == 2                        # one frame: infeasible
