@@ -139,6 +139,7 @@ def copy_calibration(mb):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persistent_batched4096_traffic.txt")
+TRAFFIC_LONG_FILE = os.path.join(ROOT, "profiles", "k_multi_long90000_traffic.txt")
 
 
 def kernel_source_hash():
@@ -146,13 +147,13 @@ def kernel_source_hash():
     return h()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the persistent kernel from the committed
-    rocprofv3 counter summary, scaled by the copy calibration; None when the
+def measured_traffic(path=None):
+    """HBM bytes per launch from a committed rocprofv3 counter summary (the
+    batched plan's by default), scaled by the copy calibration; None when the
     summary is missing or was taken on other kernel sources."""
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as fh:
+        with open(path or TRAFFIC_FILE) as fh:
             for line in fh:
                 if "=" in line and not line.startswith("#"):
                     k, v = line.split("=", 1)
@@ -306,7 +307,8 @@ def run_single(args, long_form: bool):
         "f64_rel_err": abs(float(tot) - float(t64)) / abs(float(t64)),
         "roofline": {"bound": "alu", "achieved": ops_alg / (ms / 1e3) / 1e12,
                      "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
-                     "frac": ops_alg / (ms / 1e3) / VALU_PEAK_OPS, "traffic": None,
+                     "frac": ops_alg / (ms / 1e3) / VALU_PEAK_OPS,
+                     "traffic": measured_traffic(TRAFFIC_LONG_FILE) if long_form else None,
                      "hbm_GBs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS},
         "cpu_baseline": {"value": u.T / cpu_s, "unit": "aligned frames/s", "cores": 1,
                          "kind": "oracle", "sample": "the whole utterance, one thread"},

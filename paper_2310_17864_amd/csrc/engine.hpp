@@ -368,27 +368,29 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   int u = 0;
   for (int b = 0; b < nblk && alive; ++b) {
     const int n = (nsteps - 32 * b) < kBlk ? (nsteps - 32 * b) : kBlk;
-    // cross-segment flow control, once per 32-frame block
-    // (one value past the block: the last frame reads the next one ahead; the
-    // producer publishes whole blocks, so this waits for the same event)
-    if (has_prev) {
-      if (prev_x)
-        alive &= x_pull(xl.in_ch, prev, 32 * b, n + 1, lane);   // values 32b .. 32b+n
-      else
-        alive &= wait_geq(&prev->prod, 32 * b + n + 1);
-    }
-    if (next_x)
-      alive &= x_room(xl.out_ch, 32 * b + n + 1, x_seen);
-    else if (has_next && 32 * b + n - kBnd + 1 > 0)
-      alive &= wait_geq(&next->cons, 32 * b + n - kBnd + 1);
+    // flow control with a neighbour in another workgroup: once per 32-frame
+    // block (one value past the block: the last frame reads the next one
+    // ahead)
+    if (prev_x) alive &= x_pull(xl.in_ch, prev, 32 * b, n + 1, lane);   // values 32b .. 32b+n
+    if (next_x) alive &= x_room(xl.out_ch, 32 * b + n + 1, x_seen);
     if (!alive) break;
-    float bv_c = pv->bnd[(32 * b) % kBnd];   // boundary value of the block's first frame
+    float bv_c = 0.f;
 
 #pragma unroll 1
     for (int g = 0; g < kBlk / kUnroll; ++g) {
       const int ng = n - kUnroll * g;            // frames of this group (may be < 8 or <= 0)
       if (ng <= 0) break;
       const int ubase = 32 * b + kUnroll * g;
+      const int ne = ng < kUnroll ? ng : kUnroll;
+      // flow control inside the workgroup, once per 8-frame group (one value
+      // past the group, read ahead by its last frame): a segment trails the
+      // one below by about a group, so the emission rows it reads again are
+      // still in the L2 the lower segment brought them into
+      if (has_prev && !prev_x) alive &= wait_geq(&prev->prod, ubase + ne + 1);
+      if (has_next && !next_x && ubase + ne - kBnd + 1 > 0)
+        alive &= wait_geq(&next->cons, ubase + ne - kBnd + 1);
+      if (!alive) break;
+      if (g == 0) bv_c = pv->bnd[(32 * b) % kBnd];   // boundary value of the block's first frame
       // One frame: i is the frame's static position in the group.
       auto frame = [&](auto ic) __attribute__((always_inline)) {
         constexpr int i = decltype(ic)::value;
@@ -476,15 +478,11 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
         const int sh = 32 - planes_in_word(M, q) * nf;
         dst[q * kWave] = acc[q] << sh;
       }
+      if (has_next && !next_x) lds_store_rel(&me->prod, ubase + ne + 1);
+      if (has_prev && !prev_x) lds_store_rel(&me->cons, ubase + ne);
     }
 
-    if (has_next) {
-      if (next_x)
-        x_push(xl.out_ch, me, 32 * b + 1, n, lane);             // values 32b+1 .. 32b+n
-      else
-        lds_store_rel(&me->prod, 32 * b + n + 1);
-    }
-    if (has_prev && !prev_x) lds_store_rel(&me->cons, 32 * b + n);
+    if (next_x && alive) x_push(xl.out_ch, me, 32 * b + 1, n, lane);   // values 32b+1 .. 32b+n
   }
   out.ok = alive ? 1 : 0;
   wait_dma();   // no copy into LDS may outlive this instance

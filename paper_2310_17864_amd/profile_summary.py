@@ -87,7 +87,7 @@ def traffic(fetch_dir: str, write_dir: str, out: str, copy_bytes: int, command: 
     cw = sum(v for v, _ in _per_kernel(wpath, "WRITE_SIZE", copy_kernel).values())
     fsum = sum(v for v, _ in fk.values())
     wsum = sum(v for v, _ in wk.values())
-    lines = ["# HBM traffic of one plan replay (its kernels' per-dispatch medians, summed),",
+    lines = ["# HBM traffic of one launch (per-dispatch medians of the kernels it runs, summed),",
              "# rocprofv3 --pmc, KiB per dispatch, with a plain copy of copy_bytes bytes as the scale",
              f"# command (FETCH_SIZE, then WRITE_SIZE in a second run): {command}",
              f"kernel_source_hash = {kernel_source_hash()}"]
@@ -115,11 +115,14 @@ def main(argv=None):
     b.add_argument("out")
     b.add_argument("--copy-bytes", type=int, required=True)
     b.add_argument("--command", required=True)
+    b.add_argument("--kernel", default="ctca::k_persistent",
+                   help="name prefix of the kernels whose per-dispatch traffic is summed")
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         stats(args.dir, args.out, args.command)
     else:
-        traffic(args.fetch_dir, args.write_dir, args.out, args.copy_bytes, args.command)
+        traffic(args.fetch_dir, args.write_dir, args.out, args.copy_bytes, args.command,
+                kernel=args.kernel)
 
 
 if __name__ == "__main__":

@@ -150,3 +150,25 @@ def test_server_top_segment_single_state():
     ends = {int(np.asarray(p)[-1]) != 0 for p in (b["path"].cpu().numpy() for b in bufs[:2])}
     assert ends == {True, False}                  # both end states taken
     assert res[-1][0] == 2                        # one frame: infeasible
+
+
+def test_server_restarts_after_idle():
+    # the resident kernel stops after ~20 ms without work and is started
+    # again by the next request: requests separated by idle gaps (and a burst
+    # right after a gap) all complete with the oracle's results
+    import paper_2310_17864_amd as ca
+    utts = _pool()[:9]
+    bufs = _upload(utts)
+    srv = ca.Server(64 << 30)
+    res = [None] * len(utts)
+    for i, (u, b) in enumerate(zip(utts, bufs)):
+        if i in (0, 1, 2, 3):
+            time.sleep(0.08)                      # longer than the idle stop
+            res[i] = srv.wait(srv.submit(b["em"], b["lab"], b["path"], b["sc"], b["tot"], u.blank))
+    time.sleep(0.08)
+    tickets = {i: srv.submit(bufs[i]["em"], bufs[i]["lab"], bufs[i]["path"], bufs[i]["sc"],
+                             bufs[i]["tot"], utts[i].blank) for i in range(4, len(utts))}
+    for i, t in tickets.items():
+        res[i] = srv.wait(t)
+    srv.close()
+    assert _check(utts, bufs, res) == []
