@@ -26,15 +26,18 @@ ctcalign_ctx* g_default[kMaxDevices] = {};
 
 // Sync region of multi-workgroup alignments, one per device, in uncached
 // device memory: workgroups on different XCDs poll it, and a cached copy of a
-// line in one XCD's L2 (left there by the reset kernel) would hide the other
-// XCDs' writes.  Kept for the life of the process (uncached memory is never
-// freed once a kernel has read it).  Launches that use it are serialised with
-// an event, whatever stream they come on.
+// line in one XCD's L2 would hide the other XCDs' writes.  Kept for the life
+// of the process (uncached memory is never freed once a kernel has read it).
+// Launches that use it are serialised with an event, whatever stream they
+// come on.  Each launch tags what it writes with its own generation, so the
+// region is reset only when the generations run out, and then synchronously:
+// no launch ever depends on a reset kernel queued just before it.
 struct MultiSync {
   std::mutex mu;
   XSync* region = nullptr;
   hipEvent_t last = nullptr;
   bool used = false;
+  uint32_t gen = 0;   // generation of the last launch since the last reset
 };
 MultiSync g_msync[kMaxDevices];
 
@@ -47,9 +50,17 @@ int launch_multi_serial(int device, const Inst& in, hipStream_t st) {
     HIP_TRY(hipExtMallocWithFlags(&p, sizeof(XSync), hipDeviceMallocUncached));
     m.region = static_cast<XSync*>(p);
     HIP_TRY(hipEventCreateWithFlags(&m.last, hipEventDisableTiming));
+    m.gen = kXGens - 1;   // forces the first reset
   }
   if (m.used) HIP_TRY(hipStreamWaitEvent(st, m.last, 0));
-  HIP_TRY(launch_multi(in, m.region, st));
+  if (m.gen + 1 >= (uint32_t)kXGens) {
+    // every earlier launch and the reset itself complete before the next one
+    HIP_TRY(launch_multi_reset(m.region, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    m.gen = 0;
+  }
+  ++m.gen;
+  HIP_TRY(launch_multi(in, m.region, m.gen, st));
   HIP_TRY(hipEventRecord(m.last, st));
   m.used = true;
   return CTCALIGN_OK;
@@ -68,7 +79,9 @@ int validate_one(const float* em, int32_t T, int32_t C, const int32_t* labels, i
 // Fills geometry and LDS stride fields of an Inst for a single launch.
 void geometry_one(const ctcalign_ctx* ctx, Inst& in) {
   const int S = 2 * in.L + 1;
-  const Geo g = ctx->tune.pick_one(S, in.C);
+  Geo g = ctx->tune.pick_one(S, in.C);
+  // the multi-workgroup layout tags frame indices in 21 bits
+  if (geometry_is_multi(g.W, g.M) && in.T > kXMaxT) g = ctx->tune.pick_long(S);
   in.W = g.W;
   in.M = g.M;
 }

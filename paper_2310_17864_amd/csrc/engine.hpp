@@ -211,6 +211,7 @@ struct XLink {
   XChan* out_ch = nullptr;   // ring to the upper neighbour's workgroup
   SegSync* in_lds = nullptr; // local copy of the incoming values
   int wl = 0;                // wave index in the workgroup
+  uint32_t tag = 0;          // the launch's generation tag (x_gen_tag)
 };
 
 // Polls of global memory take a round trip each: a smaller bound (~seconds).
@@ -224,17 +225,21 @@ __device__ __forceinline__ void x_store(uint64_t* p, uint64_t v) {
 }
 
 // Copies boundary values i0 .. i0+cnt-1 (cnt <= 64) from the global ring to
-// dst, waiting (bounded) until every slot holds its index.  Then tells the
-// producer how far it got.
-__device__ __forceinline__ bool x_pull(XChan* ch, SegSync* dst, int i0, int cnt, int lane) {
+// dst, waiting (bounded) until every slot holds this launch's tag and its
+// index.  Then tells the producer which values it may overwrite: those below
+// i0+cnt-1, since the next pull starts with that last value again (a
+// block's pull includes the first value of the next block).
+__device__ __forceinline__ bool x_pull(XChan* ch, SegSync* dst, int i0, int cnt, int lane, uint32_t tag) {
   const int i = i0 + lane;
   for (int it = 0; it < kXSpinLimit; ++it) {
     uint64_t v = 0;
     if (lane < cnt) v = x_load(&ch->slot[i % kXRing]);
-    const bool ok = lane >= cnt || (int32_t)(v >> 32) == i;
+    const bool ok = lane >= cnt || (uint32_t)(v >> 32) == (tag | (uint32_t)i);
     if (__builtin_amdgcn_ballot_w64(!ok) == 0) {
       if (lane < cnt) dst->bnd[i % kBnd] = __builtin_bit_cast(float, (uint32_t)v);
-      if (lane == 0) __hip_atomic_store(&ch->cons, i0 + cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      if (lane == 0)
+        __hip_atomic_store(&ch->cons, (int32_t)(tag | (uint32_t)(i0 + cnt - 1)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
       return true;
     }
     __builtin_amdgcn_s_sleep(2);
@@ -242,22 +247,25 @@ __device__ __forceinline__ bool x_pull(XChan* ch, SegSync* dst, int i0, int cnt,
   return false;
 }
 
-// Waits (bounded) until the consumer has taken every value that slot reuse
-// up to index i_end (exclusive) would overwrite.  `seen` caches its progress.
-__device__ __forceinline__ bool x_room(XChan* ch, int i_end, int& seen) {
+// Waits (bounded) until the consumer has released every value that slot
+// reuse up to index i_end (exclusive) would overwrite (those below
+// i_end - kXRing).  `seen` caches its progress; a count left by another
+// launch (other tag) counts as none.
+__device__ __forceinline__ bool x_room(XChan* ch, int i_end, int& seen, uint32_t tag) {
   for (int it = 0; it < kXSpinLimit && i_end - kXRing > seen; ++it) {
-    seen = __hip_atomic_load(&ch->cons, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const uint32_t c = (uint32_t)__hip_atomic_load(&ch->cons, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if ((c & ~kXIdxMask) == tag) seen = (int)(c & kXIdxMask);
     if (i_end - kXRing > seen) __builtin_amdgcn_s_sleep(2);
   }
   return i_end - kXRing <= seen;
 }
 
 // Publishes boundary values i0 .. i0+cnt-1 (cnt <= 64) of src to the ring.
-__device__ __forceinline__ void x_push(XChan* ch, const SegSync* src, int i0, int cnt, int lane) {
+__device__ __forceinline__ void x_push(XChan* ch, const SegSync* src, int i0, int cnt, int lane, uint32_t tag) {
   if (lane < cnt) {
     const int i = i0 + lane;
     const uint32_t bits = __builtin_bit_cast(uint32_t, src->bnd[i % kBnd]);
-    x_store(&ch->slot[i % kXRing], ((uint64_t)(uint32_t)i << 32) | bits);
+    x_store(&ch->slot[i % kXRing], ((uint64_t)(tag | (uint32_t)i) << 32) | bits);
   }
 }
 
@@ -328,7 +336,7 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   if (has_next) {
     if (lane == kWave - 1) me->bnd[0] = a[M - 1];
     if (next_x)
-      x_push(xl.out_ch, me, 0, 1, lane);
+      x_push(xl.out_ch, me, 0, 1, lane, xl.tag);
     else
       lds_store_rel(&me->prod, 1);
   }
@@ -364,6 +372,10 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0;
 
+  // neighbours in one workgroup hand over boundary values every 8-frame
+  // group in the batched and single kernels, every 32-frame block in the
+  // multi-workgroup layout (its frames are short: few states per lane)
+  constexpr bool kGroupFlow = !kX;
   bool alive = true;
   int u = 0;
   for (int b = 0; b < nblk && alive; ++b) {
@@ -371,8 +383,13 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
     // flow control with a neighbour in another workgroup: once per 32-frame
     // block (one value past the block: the last frame reads the next one
     // ahead)
-    if (prev_x) alive &= x_pull(xl.in_ch, prev, 32 * b, n + 1, lane);   // values 32b .. 32b+n
-    if (next_x) alive &= x_room(xl.out_ch, 32 * b + n + 1, x_seen);
+    if (prev_x) alive &= x_pull(xl.in_ch, prev, 32 * b, n + 1, lane, xl.tag);   // values 32b .. 32b+n
+    if (next_x) alive &= x_room(xl.out_ch, 32 * b + n + 1, x_seen, xl.tag);
+    if constexpr (!kGroupFlow) {
+      if (has_prev && !prev_x) alive &= wait_geq(&prev->prod, 32 * b + n + 1);
+      if (has_next && !next_x && 32 * b + n - kBnd + 1 > 0)
+        alive &= wait_geq(&next->cons, 32 * b + n - kBnd + 1);
+    }
     if (!alive) break;
     float bv_c = 0.f;
 
@@ -386,10 +403,12 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
       // past the group, read ahead by its last frame): a segment trails the
       // one below by about a group, so the emission rows it reads again are
       // still in the L2 the lower segment brought them into
-      if (has_prev && !prev_x) alive &= wait_geq(&prev->prod, ubase + ne + 1);
-      if (has_next && !next_x && ubase + ne - kBnd + 1 > 0)
-        alive &= wait_geq(&next->cons, ubase + ne - kBnd + 1);
-      if (!alive) break;
+      if constexpr (kGroupFlow) {
+        if (has_prev && !prev_x) alive &= wait_geq(&prev->prod, ubase + ne + 1);
+        if (has_next && !next_x && ubase + ne - kBnd + 1 > 0)
+          alive &= wait_geq(&next->cons, ubase + ne - kBnd + 1);
+        if (!alive) break;
+      }
       if (g == 0) bv_c = pv->bnd[(32 * b) % kBnd];   // boundary value of the block's first frame
       // One frame: i is the frame's static position in the group.
       auto frame = [&](auto ic) __attribute__((always_inline)) {
@@ -478,11 +497,17 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
         const int sh = 32 - planes_in_word(M, q) * nf;
         dst[q * kWave] = acc[q] << sh;
       }
-      if (has_next && !next_x) lds_store_rel(&me->prod, ubase + ne + 1);
-      if (has_prev && !prev_x) lds_store_rel(&me->cons, ubase + ne);
+      if constexpr (kGroupFlow) {
+        if (has_next && !next_x) lds_store_rel(&me->prod, ubase + ne + 1);
+        if (has_prev && !prev_x) lds_store_rel(&me->cons, ubase + ne);
+      }
     }
 
-    if (next_x && alive) x_push(xl.out_ch, me, 32 * b + 1, n, lane);   // values 32b+1 .. 32b+n
+    if (next_x && alive) x_push(xl.out_ch, me, 32 * b + 1, n, lane, xl.tag);   // values 32b+1 .. 32b+n
+    if constexpr (!kGroupFlow) {
+      if (has_next && !next_x) lds_store_rel(&me->prod, 32 * b + n + 1);
+      if (has_prev && !prev_x) lds_store_rel(&me->cons, 32 * b + n);
+    }
   }
   out.ok = alive ? 1 : 0;
   wait_dma();   // no copy into LDS may outlive this instance

@@ -38,21 +38,30 @@ struct Inst {
 // Long alignments spread over several workgroups ("multi" layout): segment w
 // runs on wave w % kXWaves of workgroup w / kXWaves.  Neighbouring segments in
 // different workgroups exchange boundary values through a ring of 64-bit
-// slots in global memory, each holding (value bits, frame index) so that a
-// reader recognises a slot written for the index it wants; all accesses are
-// relaxed atomics.  The region lives in uncached device memory (one per
-// device) and is reset (every word -1) before each launch.
+// slots in global memory, each holding (value bits, tag) so that a reader
+// recognises a slot written for the index it wants; all accesses are relaxed
+// atomics.  Every word a launch writes carries its tag: the launch's
+// generation g (1 .. kXGens-1) in the top bits and the frame index or count
+// below, so words left by earlier launches never match and the region needs
+// no reset between launches (the host resets it, synchronously, once per
+// kXGens-1 launches).  The region lives in uncached device memory (one per
+// device).
 constexpr int kXWaves = 8;        // waves per workgroup
 constexpr int kXMaxGroups = 32;   // workgroups per alignment
 constexpr int kXRing = 512;       // slots per cross-workgroup boundary
+constexpr int kXIdxBits = 21;     // frame index / count field of a tag
+constexpr uint32_t kXIdxMask = (1u << kXIdxBits) - 1;
+constexpr int kXGens = 1024;      // generations between resets
+constexpr int kXMaxT = (1 << kXIdxBits) - 64;   // longest alignment of the layout
+__host__ __device__ constexpr uint32_t x_gen_tag(uint32_t gen) { return gen << kXIdxBits; }
 struct XChan {
-  uint64_t slot[kXRing];
-  int32_t cons;                   // frames the consumer has taken (next index it needs)
+  uint64_t slot[kXRing];          // (tag | frame index) << 32 | value bits
+  int32_t cons;                   // tag | frames the consumer has taken
   int32_t pad[31];
 };
 struct XSync {
   XChan ch[kXMaxGroups - 1];      // ch[g]: from workgroup g to workgroup g+1
-  int32_t done[kXWaves * kXMaxGroups];   // 1 once segment w's backpointers are visible
+  int32_t done[kXWaves * kXMaxGroups];   // tag | 1 once segment w's backpointers are visible
 };
 __host__ __device__ constexpr bool geometry_is_multi(int W, int M) { return M <= 16 && W > 4; }
 
@@ -78,14 +87,23 @@ struct PadDesc {
 // and stores to it (no read-modify-write), so there is no cross-workgroup
 // atomic on the device at all.
 constexpr int kServeWaves = 16;
+constexpr int kServeMaxParts = 4;   // workgroups one served alignment may span
+enum : int32_t {
+  kItemSegments = 0,   // waves run segments of the item's alignments (which/seg/first)
+  kItemPart = 1,       // part `part` of `nparts` of inst[0] in the multi-workgroup layout
+  kItemReset = 2,      // set every word of the sync region xs to -1
+};
 struct ServeItem {                // one workgroup's work: up to 16 segments
   Inst inst[kServeWaves];         // the item's alignments
   int8_t which[kServeWaves];      // wave -> index into inst (-1: idle wave)
   int8_t seg[kServeWaves];        // wave -> segment of that alignment
   int8_t first[kServeWaves];      // wave -> first wave of that alignment
   int32_t npad;                   // 1: copy pad.src into pad.dst (inst[0]'s rows) first
-  int32_t pad1_;
+  int32_t kind;                   // kItem*
   PadDesc pad;
+  XSync* xs;                      // kItemPart / kItemReset: the sync region
+  uint32_t xtag;                  // kItemPart: the generation tag of this alignment
+  int16_t part, nparts;           // kItemPart: segments 16*part .. 16*part+15
 };
 static_assert(sizeof(ServeItem) % 8 == 0, "items are copied in 8-byte words");
 struct ServeBox {                 // per resident workgroup b (host memory)

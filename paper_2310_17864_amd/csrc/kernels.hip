@@ -204,6 +204,77 @@ k_persistent_crit(const Inst* __restrict__ insts, const int* __restrict__ order,
 
 #undef CTCA_CASE
 
+// ---- multi layout: one long alignment over several workgroups ---------------
+
+__device__ __forceinline__ bool wait_eq_sys(const int* p, int want) {
+  for (int n = 0; n < kXSpinLimit; ++n) {
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) == want) return true;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return false;
+}
+
+// Segment w = g * kWG + wl of a multi-workgroup alignment on wave wl of
+// workgroup g (kWG waves per workgroup; sy[kWG] holds the incoming copy).
+template <int M, int kWG>
+__device__ __forceinline__ void run_multi(const Inst& in, XSync* xs, uint32_t tag, SegSync* sy,
+                                          const Ring& ring, int g, int wl, int lane, bool bad) {
+  const int w = g * kWG + wl;
+  if (w >= in.W) return;
+  XLink xl;
+  xl.wl = wl;
+  xl.tag = tag;
+  xl.in_lds = sy + kWG;
+  if (wl == 0 && g > 0) xl.in_ch = &xs->ch[g - 1];
+  if (wl == kWG - 1 && w + 1 < in.W) xl.out_ch = &xs->ch[g];
+  const FwdOut fo = segment_forward<M, true>(in, w, lane, ring, sy, bad, xl);
+  if (w + 1 < in.W) {
+    // backpointers visible device-wide, then the flag
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0)
+      __hip_atomic_store(&xs->done[w], (int)(tag | 1u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  } else {
+    bool ok = fo.ok != 0;
+    for (int k = 0; k + 1 < in.W; ++k) ok &= wait_eq_sys(&xs->done[k], (int)(tag | 1u));
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    FwdOut f2 = fo;
+    f2.ok = ok ? 1 : 0;
+    backtrack<M>(in, f2, bad ? kEinval : kOk, lane);
+  }
+}
+
+// Workgroup g runs segments 8g .. 8g+7 of one alignment; all workgroups are
+// resident together (one launch of at most kXMaxGroups workgroups).  Every
+// workgroup validates the whole transcript itself, so the verdict needs no
+// communication between workgroups.  `tag` marks every word this launch
+// writes to the sync region.
+__global__ void __launch_bounds__(kWave * kXWaves) k_multi(Inst in, XSync* xs, uint32_t tag) {
+  __shared__ SegSync sy[kXWaves + 1];   // + the copy of the incoming boundary
+  __shared__ __attribute__((aligned(16))) float ring[kXWaves][kRing * kMaxC];
+  const int wl = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  reset_sync(sy + wl, lane);
+  if (wl == 0) reset_sync(sy + kXWaves, lane);
+  bool bad = false;
+  for (int i = threadIdx.x; i < in.L; i += blockDim.x) {
+    const int v = in.lab[i];
+    bad |= (v < 0) | (v >= in.C) | (v == in.blank);
+  }
+  bad = __syncthreads_or(bad);
+  const int g = blockIdx.x;
+  const Ring r{ring[wl]};
+  switch (in.M) {
+    case 2: run_multi<2, kXWaves>(in, xs, tag, sy, r, g, wl, lane, bad); break;
+    case 4: run_multi<4, kXWaves>(in, xs, tag, sy, r, g, wl, lane, bad); break;
+    case 6: run_multi<6, kXWaves>(in, xs, tag, sy, r, g, wl, lane, bad); break;
+    case 8: run_multi<8, kXWaves>(in, xs, tag, sy, r, g, wl, lane, bad); break;
+    case 10: run_multi<10, kXWaves>(in, xs, tag, sy, r, g, wl, lane, bad); break;
+    case 12: run_multi<12, kXWaves>(in, xs, tag, sy, r, g, wl, lane, bad); break;
+    case 14: run_multi<14, kXWaves>(in, xs, tag, sy, r, g, wl, lane, bad); break;
+    case 16: run_multi<16, kXWaves>(in, xs, tag, sy, r, g, wl, lane, bad); break;
+    default: break;
+  }
+}
+
 // ---- resident serving kernel -------------------------------------------------
 
 // Loads from fine-grained host memory at system scope: never served from a
@@ -239,7 +310,7 @@ constexpr uint64_t kServeIdle = ~0ull, kServeExit = ~0ull - 1;
 // clock without work.
 __global__ void __launch_bounds__(kWave * kServeWaves)
 k_serve(const ServeItem* items, ServeBox* box, const int32_t* stop, uint64_t epoch, int64_t idle_limit) {
-  __shared__ SegSync sy[kServeWaves];
+  __shared__ SegSync sy[kServeWaves + 1];   // + the incoming copy of a multi-workgroup part
   __shared__ __attribute__((aligned(16))) float ring[kServeWaves][kRing * kMaxC];
   __shared__ uint64_t s_item[sizeof(ServeItem) / 8];
   __shared__ uint64_t s_cmd;
@@ -294,9 +365,36 @@ k_serve(const ServeItem* items, ServeBox* box, const int32_t* stop, uint64_t epo
     const uint64_t* src = reinterpret_cast<const uint64_t*>(items + blockIdx.x);
     for (int k = tid; k < (int)(sizeof(ServeItem) / 8); k += kWave * kServeWaves) s_item[k] = host_load(src + k);
     reset_sync(sy + w, lane);
+    if (w == 0) reset_sync(sy + kServeWaves, lane);
     __syncthreads();
     const ServeItem* it = reinterpret_cast<const ServeItem*>(s_item);
-    if (__builtin_amdgcn_readfirstlane(it->npad)) {
+    const int kind = __builtin_amdgcn_readfirstlane(it->kind);
+    if (kind == kItemReset) {
+      // a tag no alignment uses, in every word of the sync region
+      int* p = reinterpret_cast<int*>(it->xs);
+      for (int i = tid; i < (int)(sizeof(XSync) / sizeof(int)); i += kWave * kServeWaves) p[i] = -1;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    } else if (kind == kItemPart) {
+      // one workgroup of a multi-workgroup alignment: every part checks the
+      // whole transcript, so the verdict needs no exchange
+      const Inst in = uniform_inst(&it->inst[0]);
+      bool bad = false;
+      for (int i = tid; i < in.L; i += kWave * kServeWaves) {
+        const int v = in.lab[i];
+        bad |= (v < 0) | (v >= in.C) | (v == in.blank);
+      }
+      bad = __syncthreads_or(bad);
+      const int part = __builtin_amdgcn_readfirstlane((int)it->part);
+      XSync* xs = it->xs;
+      const uint32_t tag = (uint32_t)__builtin_amdgcn_readfirstlane((int)it->xtag);
+      const Ring r{ring[w]};
+      switch (in.M) {
+        case 4: run_multi<4, kServeWaves>(in, xs, tag, sy, r, part, w, lane, bad); break;
+        case 6: run_multi<6, kServeWaves>(in, xs, tag, sy, r, part, w, lane, bad); break;
+        case 8: run_multi<8, kServeWaves>(in, xs, tag, sy, r, part, w, lane, bad); break;
+        default: break;
+      }
+    } else if (__builtin_amdgcn_readfirstlane(it->npad)) {
       // emission rows into the compiled stride (zeros in the pad columns)
       const PadDesc pd = it->pad;
       const int64_t n = (int64_t)pd.T * pd.stride;
@@ -309,14 +407,16 @@ k_serve(const ServeItem* items, ServeBox* box, const int32_t* stop, uint64_t epo
       __syncthreads();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    const int wi = __builtin_amdgcn_readfirstlane((int)it->which[w]);
-    if (wi < 0) {
-      __syncthreads();   // the barrier the busy waves take inside run_wave
-    } else {
-      const Inst in = uniform_inst(&it->inst[wi]);
-      const int seg = __builtin_amdgcn_readfirstlane((int)it->seg[w]);
-      const int first = __builtin_amdgcn_readfirstlane((int)it->first[w]);
-      pack_dispatch(in, seg, lane, sy + first, Ring{ring[w]});
+    if (kind == kItemSegments) {
+      const int wi = __builtin_amdgcn_readfirstlane((int)it->which[w]);
+      if (wi < 0) {
+        __syncthreads();   // the barrier the busy waves take inside run_wave
+      } else {
+        const Inst in = uniform_inst(&it->inst[wi]);
+        const int seg = __builtin_amdgcn_readfirstlane((int)it->seg[w]);
+        const int first = __builtin_amdgcn_readfirstlane((int)it->first[w]);
+        pack_dispatch(in, seg, lane, sy + first, Ring{ring[w]});
+      }
     }
     __syncthreads();                    // the item's LDS is free again
     if (tid == 0) {
@@ -328,72 +428,6 @@ k_serve(const ServeItem* items, ServeBox* box, const int32_t* stop, uint64_t epo
   }
 }
 
-
-// ---- multi layout: one long alignment over several workgroups ---------------
-
-__device__ __forceinline__ bool wait_geq_agent(int* p, int need) {
-  for (int n = 0; n < kXSpinLimit; ++n) {
-    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) >= need) return true;
-    __builtin_amdgcn_s_sleep(2);
-  }
-  return false;
-}
-
-template <int M>
-__device__ __forceinline__ void run_multi(const Inst& in, XSync* xs, SegSync* sy, const Ring& ring,
-                                          int g, int wl, int lane, bool bad) {
-  const int w = g * kXWaves + wl;
-  if (w >= in.W) return;
-  XLink xl;
-  xl.wl = wl;
-  xl.in_lds = sy + kXWaves;
-  if (wl == 0 && g > 0) xl.in_ch = &xs->ch[g - 1];
-  if (wl == kXWaves - 1 && w + 1 < in.W) xl.out_ch = &xs->ch[g];
-  const FwdOut fo = segment_forward<M, true>(in, w, lane, ring, sy, bad, xl);
-  if (w + 1 < in.W) {
-    // backpointers visible device-wide, then the flag
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (lane == 0) __hip_atomic_store(&xs->done[w], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  } else {
-    bool ok = fo.ok != 0;
-    for (int k = 0; k + 1 < in.W; ++k) ok &= wait_geq_agent(&xs->done[k], 1);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    FwdOut f2 = fo;
-    f2.ok = ok ? 1 : 0;
-    backtrack<M>(in, f2, bad ? kEinval : kOk, lane);
-  }
-}
-
-// Workgroup g runs segments 8g .. 8g+7 of one alignment; all workgroups are
-// resident together (one launch of at most kXMaxGroups workgroups).  Every
-// workgroup validates the whole transcript itself, so the verdict needs no
-// communication between workgroups.
-__global__ void __launch_bounds__(kWave * kXWaves) k_multi(Inst in, XSync* xs) {
-  __shared__ SegSync sy[kXWaves + 1];   // + the copy of the incoming boundary
-  __shared__ __attribute__((aligned(16))) float ring[kXWaves][kRing * kMaxC];
-  const int wl = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  reset_sync(sy + wl, lane);
-  if (wl == 0) reset_sync(sy + kXWaves, lane);
-  bool bad = false;
-  for (int i = threadIdx.x; i < in.L; i += blockDim.x) {
-    const int v = in.lab[i];
-    bad |= (v < 0) | (v >= in.C) | (v == in.blank);
-  }
-  bad = __syncthreads_or(bad);
-  const int g = blockIdx.x;
-  const Ring r{ring[wl]};
-  switch (in.M) {
-    case 2: run_multi<2>(in, xs, sy, r, g, wl, lane, bad); break;
-    case 4: run_multi<4>(in, xs, sy, r, g, wl, lane, bad); break;
-    case 6: run_multi<6>(in, xs, sy, r, g, wl, lane, bad); break;
-    case 8: run_multi<8>(in, xs, sy, r, g, wl, lane, bad); break;
-    case 10: run_multi<10>(in, xs, sy, r, g, wl, lane, bad); break;
-    case 12: run_multi<12>(in, xs, sy, r, g, wl, lane, bad); break;
-    case 14: run_multi<14>(in, xs, sy, r, g, wl, lane, bad); break;
-    case 16: run_multi<16>(in, xs, sy, r, g, wl, lane, bad); break;
-    default: break;
-  }
-}
 
 __global__ void __launch_bounds__(256) k_pad(const PadDesc* __restrict__ d) {
   const PadDesc pd = d[blockIdx.y];
@@ -508,17 +542,23 @@ hipError_t launch_one(const Inst& in, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_multi(const Inst& in, XSync* xs, hipStream_t st) {
-  // every slot index and flag starts at -1 (a fill kernel: graph-capturable)
+hipError_t launch_multi_reset(XSync* xs, hipStream_t st) {
+  // every slot, count and flag -1: a tag no launch uses
   const int nwords = (int)(sizeof(XSync) / sizeof(int));
   hipLaunchKernelGGL(k_fill, dim3((nwords + 255) / 256), dim3(256), 0, st, reinterpret_cast<int*>(xs),
                      nwords, -1);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi(const Inst& in, XSync* xs, uint32_t gen, hipStream_t st) {
+  if (gen < 1 || gen >= (uint32_t)kXGens || in.T > kXMaxT) return hipErrorInvalidValue;
   const int groups = (in.W + kXWaves - 1) / kXWaves;
   // the workgroups wait on each other: a cooperative launch guarantees they
   // are all resident at once (or fails instead of starting)
   Inst in_copy = in;
   XSync* xs_copy = xs;
-  void* args[] = {&in_copy, &xs_copy};
+  uint32_t tag = x_gen_tag(gen);
+  void* args[] = {&in_copy, &xs_copy, &tag};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_multi), dim3(groups),
                                     dim3(kWave * kXWaves), args, 0, st);
 }
@@ -585,6 +625,12 @@ hipError_t launch_serve(const ServeItem* d_items, ServeBox* d_box, const int32_t
 
 bool geometry_supported_serve(int W, int M) {
   return W >= 1 && W <= kServeWaves && m_in(M, kPackMenuK, 8);
+}
+
+static const int kServePartMenu[] = {4, 6, 8};
+bool geometry_supported_serve_parts(int W, int M) {
+  return W > 0 && W <= kServeWaves * kServeMaxParts && W <= kXWaves * kXMaxGroups &&
+         m_in(M, kServePartMenu, 3);
 }
 
 int persistent_blocks_per_cu() {

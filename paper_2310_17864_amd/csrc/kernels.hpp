@@ -9,8 +9,11 @@ namespace ctca {
 bool geometry_supported_one(int W, int M);
 bool geometry_supported_pack(int W, int M);
 hipError_t launch_one(const Inst& in, hipStream_t st);
-// one long alignment over ceil(W/8) workgroups; xs: its sync region (reset here)
-hipError_t launch_multi(const Inst& in, XSync* xs, hipStream_t st);
+// one long alignment over ceil(W/8) workgroups; xs: its sync region, gen:
+// the launch's generation (1 .. kXGens-1, distinct since the last reset)
+hipError_t launch_multi(const Inst& in, XSync* xs, uint32_t gen, hipStream_t st);
+// sets the whole sync region to -1 (to be complete before the next launch)
+hipError_t launch_multi_reset(XSync* xs, hipStream_t st);
 hipError_t launch_persistent(const Inst* d_insts, const Pack* d_packs, int npacks, int* d_head,
                              int grid, hipStream_t st, int64_t* d_trace = nullptr);
 hipError_t launch_fill(int* p, int n, int v, hipStream_t st);
@@ -31,5 +34,7 @@ int persistent_blocks_per_cu();
 hipError_t launch_serve(const ServeItem* d_items, ServeBox* d_box, const int32_t* d_stop,
                         uint64_t epoch, int64_t idle_limit, int grid, hipStream_t st);
 bool geometry_supported_serve(int W, int M);
+// the serving kernel's multi-workgroup parts: W <= 64 segments, M in {4, 6, 8}
+bool geometry_supported_serve_parts(int W, int M);
 
 }  // namespace ctca

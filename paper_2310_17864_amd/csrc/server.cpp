@@ -42,14 +42,40 @@ constexpr int kMaxBatch = 1024;       // requests per admitted group
 constexpr int kFlags = 1 << 16;       // completion flags (requests in flight)
 constexpr double kIdleStop = 0.02;    // seconds without work before the kernel is stopped
 constexpr int64_t kDeviceIdle = 1000000000;  // a workgroup's own idle limit: 10 s of the 100 MHz clock
+constexpr int kRegions = 8;           // sync regions: large alignments spread over workgroups at once
+constexpr int kMaxDev = 64;
 
 struct Payload {
   ctcalign_request req;
-  Geo g;
-  size_t bp_bytes;  // workspace part for backpointers
+  Geo g;            // layout on one resident workgroup
+  Geo gp;           // layout over several resident workgroups (W = 0: none)
+  size_t bp_bytes;  // workspace part for backpointers (the larger of the two layouts)
   size_t pad_bytes; // workspace part for a padded emission copy (0 if none)
   int stride;
 };
+
+// Sync regions of multi-workgroup alignments live in uncached device memory,
+// which is never freed once a kernel has read it: servers take them from a
+// per-device pool and give them back.
+std::mutex g_xpool_mu;
+std::vector<XSync*> g_xpool[kMaxDev];
+
+XSync* xpool_take(int dev) {
+  std::lock_guard<std::mutex> lk(g_xpool_mu);
+  if (!g_xpool[dev].empty()) {
+    XSync* x = g_xpool[dev].back();
+    g_xpool[dev].pop_back();
+    return x;
+  }
+  void* p = nullptr;
+  if (hipExtMallocWithFlags(&p, sizeof(XSync), hipDeviceMallocUncached) != hipSuccess) return nullptr;
+  return static_cast<XSync*>(p);
+}
+
+void xpool_give(int dev, XSync* x) {
+  std::lock_guard<std::mutex> lk(g_xpool_mu);
+  g_xpool[dev].push_back(x);
+}
 
 // 16-wave pack of small alignments (pack_by_width's layout)
 struct Pack16 {
@@ -76,6 +102,7 @@ class ServeExec {
 
   int init() {
     grid_ = std::max(ctx_->num_cu, 1);
+    if (ctx_->device < 0 || ctx_->device >= kMaxDev) return CTCALIGN_EDEVICE;
     HIP_TRY(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&ended_, hipEventDisableTiming));
     int rc;
@@ -83,8 +110,17 @@ class ServeExec {
         (rc = host_alloc(&h_stop_, &d_stop_, 16)) || (rc = host_alloc(&h_flag_, &d_flag_, kFlags)))
       return rc;
     sent_.assign(grid_, 0);
+    reset_of_.assign(grid_, -1);
+    flag_region_.assign(kFlags, -1);
     free_flag_.reserve(kFlags);
     for (int i = kFlags - 1; i >= 0; --i) free_flag_.push_back(i);
+    // sync regions: each is reset by the kernel before its first use
+    for (int r = 0; r < kRegions; ++r) {
+      XSync* x = xpool_take(ctx_->device);
+      if (!x) return CTCALIGN_ENOMEM;
+      regions_.push_back(Region{x, 0, false, false});
+      schedule_reset(r);
+    }
     return CTCALIGN_OK;
   }
 
@@ -96,6 +132,8 @@ class ServeExec {
     if (stream_) (void)hipStreamDestroy(stream_);
     for (void* h : {(void*)h_items_, (void*)h_box_, (void*)h_stop_, (void*)h_flag_})
       if (h) (void)hipHostFree(h);
+    for (auto& r : regions_) xpool_give(ctx_->device, r.xs);
+    regions_.clear();
     h_items_ = nullptr;
     h_box_ = nullptr;
     h_stop_ = nullptr;
@@ -122,7 +160,29 @@ class ServeExec {
       free_flag_.pop_back();
       __atomic_store_n(h_flag_ + f, -1, __ATOMIC_RELEASE);
       h.flag[k] = f;
-      insts[k] = make_inst(*p, reqs[k]->arena_off, d_flag_ + f);
+      const int r = p->gp.W > 0 ? free_region() : -1;
+      if (r >= 0) {
+        // over several resident workgroups, tagged with the region's next
+        // generation
+        Region& rg = regions_[r];
+        rg.busy = true;
+        ++rg.gen;
+        flag_region_[f] = r;
+        const Inst in = make_inst(*p, p->gp, reqs[k]->arena_off, d_flag_ + f);
+        const int nparts = (in.W + kServeWaves - 1) / kServeWaves;
+        for (int part = 0; part < nparts; ++part) {
+          ServeItem it = blank_item();
+          it.kind = kItemPart;
+          it.inst[0] = in;
+          it.xs = rg.xs;
+          it.xtag = x_gen_tag(rg.gen);
+          it.part = (int16_t)part;
+          it.nparts = (int16_t)nparts;
+          pending_.push_back(it);
+        }
+        continue;
+      }
+      insts[k] = make_inst(*p, p->g, reqs[k]->arena_off, d_flag_ + f);
       if (p->pad_bytes || p->g.W > kPackWaves) {
         ServeItem it = blank_item();
         it.inst[0] = insts[k];
@@ -183,6 +243,11 @@ class ServeExec {
     for (size_t k = 0; k < reqs.size(); ++k) {
       st[k] = __atomic_load_n(h_flag_ + h.flag[k], __ATOMIC_ACQUIRE);
       if (st[k] < 0 && launch_failed_ && !running_) st[k] = CTCALIGN_EDEVICE;
+      if (st[k] >= 0 && flag_region_[h.flag[k]] >= 0) {
+        // the top segment finishes last: the region is no longer in use
+        release_region(flag_region_[h.flag[k]]);
+        flag_region_[h.flag[k]] = -1;
+      }
       all &= st[k] >= 0;
     }
     return all;
@@ -222,21 +287,44 @@ class ServeExec {
       last_work_ = mono_now();
     }
     if (!running_ || stopping_) return;
-    for (int n = 0; n < grid_ && !pending_.empty(); ++n) {
-      const int b = rr_;
-      rr_ = (rr_ + 1) % grid_;
+    // idle workgroups (round robin from rr_); a finished reset frees its region
+    std::vector<int> idle;
+    for (int n = 0; n < grid_; ++n) {
+      const int b = (rr_ + n) % grid_;
       const uint64_t live = __atomic_load_n(&h_box_[b].live, __ATOMIC_ACQUIRE);
       const uint64_t ack = __atomic_load_n(&h_box_[b].ack, __ATOMIC_ACQUIRE);
-      if (live != epoch_ || ack != sent_[b]) continue;
-      std::memcpy((void*)&h_items_[b], &pending_.front(), sizeof(ServeItem));
-      pending_.pop_front();
-      ++sent_[b];
-      __atomic_store_n(&h_box_[b].mail, sent_[b] << 32, __ATOMIC_RELEASE);
-      // a workgroup leaving withdraws `live` before its last look at the
-      // mailbox: if it is gone now, it may not have seen this item, and a
-      // restarted kernel runs it
-      __atomic_thread_fence(__ATOMIC_SEQ_CST);
-      if (__atomic_load_n(&h_box_[b].live, __ATOMIC_ACQUIRE) != epoch_) {
+      if (ack != sent_[b]) continue;
+      if (reset_of_[b] >= 0) {
+        regions_[reset_of_[b]].gen = 0;
+        regions_[reset_of_[b]].resetting = false;
+        reset_of_[b] = -1;
+      }
+      if (live == epoch_) idle.push_back(b);
+    }
+    // hand out items in order; the parts of one alignment go out together
+    // (they wait on each other), or not at all this round
+    size_t next = 0;
+    while (!pending_.empty()) {
+      const ServeItem& head = pending_.front();
+      const size_t unit = head.kind == kItemPart ? (size_t)head.nparts : 1;
+      if (idle.size() - next < unit) break;
+      bool gone = false;
+      for (size_t u = 0; u < unit; ++u) {
+        const int b = idle[next++];
+        rr_ = (b + 1) % grid_;
+        const ServeItem& it = pending_.front();
+        if (it.kind == kItemReset) reset_of_[b] = region_of(it.xs);
+        std::memcpy((void*)&h_items_[b], &it, sizeof(ServeItem));
+        pending_.pop_front();
+        ++sent_[b];
+        __atomic_store_n(&h_box_[b].mail, sent_[b] << 32, __ATOMIC_RELEASE);
+        // a workgroup leaving withdraws `live` before its last look at the
+        // mailbox: if it is gone now, it may not have seen this item, and a
+        // restarted kernel runs it
+        __atomic_thread_fence(__ATOMIC_SEQ_CST);
+        gone |= __atomic_load_n(&h_box_[b].live, __ATOMIC_ACQUIRE) != epoch_;
+      }
+      if (gone) {
         stopping_ = true;
         __atomic_store_n(h_stop_, 1, __ATOMIC_RELEASE);
         break;
@@ -255,6 +343,41 @@ class ServeExec {
   bool launch_failed() const { return launch_failed_; }
 
  private:
+  struct Region {
+    XSync* xs;
+    uint32_t gen;      // generation of its last alignment since the last reset
+    bool busy;         // an alignment uses it
+    bool resetting;    // its reset item has not been acknowledged yet
+  };
+
+  int free_region() const {
+    for (size_t r = 0; r < regions_.size(); ++r)
+      if (!regions_[r].busy && !regions_[r].resetting && regions_[r].gen + 1 < (uint32_t)kXGens)
+        return (int)r;
+    return -1;
+  }
+
+  int region_of(const XSync* xs) const {
+    for (size_t r = 0; r < regions_.size(); ++r)
+      if (regions_[r].xs == xs) return (int)r;
+    return -1;
+  }
+
+  // a reset item goes to the front of the queue; the region is usable again
+  // once a workgroup has acknowledged it
+  void schedule_reset(int r) {
+    regions_[r].resetting = true;
+    ServeItem it = blank_item();
+    it.kind = kItemReset;
+    it.xs = regions_[r].xs;
+    pending_.push_front(it);
+  }
+
+  void release_region(int r) {
+    regions_[r].busy = false;
+    if (regions_[r].gen + 1 >= (uint32_t)kXGens) schedule_reset(r);
+  }
+
   bool any_unacked() const {
     for (int b = 0; b < grid_; ++b)
       if (__atomic_load_n(&h_box_[b].ack, __ATOMIC_ACQUIRE) != sent_[b]) return true;
@@ -272,7 +395,7 @@ class ServeExec {
     return it;
   }
 
-  Inst make_inst(const Payload& p, size_t off, int32_t* notify) {
+  Inst make_inst(const Payload& p, Geo g, size_t off, int32_t* notify) {
     Inst in{};
     in.T = p.req.T;
     in.C = p.req.C;
@@ -284,8 +407,8 @@ class ServeExec {
     in.total = p.req.out_total;
     in.status = nullptr;
     in.notify = notify;
-    in.W = p.g.W;
-    in.M = p.g.M;
+    in.W = g.W;
+    in.M = g.M;
     in.stride = p.stride;
     in.prio = 0;
     in.bp = reinterpret_cast<uint32_t*>(arena_ + off);
@@ -305,6 +428,9 @@ class ServeExec {
   std::vector<uint64_t> sent_;       // per workgroup: sequence of the last item posted
   std::vector<int> free_flag_;
   std::deque<ServeItem> pending_;    // items waiting for an idle workgroup
+  std::vector<Region> regions_;
+  std::vector<int> reset_of_;        // per workgroup: region its unacknowledged reset item clears
+  std::vector<int> flag_region_;     // per completion flag: region its alignment uses
   uint64_t epoch_ = 0;
   int rr_ = 0;
   bool running_ = false, stopping_ = false, launch_failed_ = false;
@@ -421,6 +547,16 @@ int ctcalign_server_submit(ctcalign_server* s, const ctcalign_request* r, uint64
   p->pad_bytes = (r->C != p->stride || !aligned16(r->emission))
                      ? round_up((size_t)r->T * p->stride * sizeof(float), 256)
                      : 0;
+  // large unpadded requests may run over several workgroups (when a sync
+  // region is free at launch): the workspace holds either layout
+  p->gp = Geo{0, 0};
+  if (S > s->ctx->tune.max_pack_states() && !p->pad_bytes && r->T <= kXMaxT) {
+    const Geo gp = s->ctx->tune.pick_serve_parts(S);
+    if (gp.W > 0 && geometry_supported_serve_parts(gp.W, gp.M)) {
+      p->gp = gp;
+      p->bp_bytes = std::max(p->bp_bytes, round_up((size_t)bp_words(r->T, gp.W, gp.M) * 4, 256));
+    }
+  }
   SchedReq* q = new (std::nothrow) SchedReq();
   if (!q) {
     delete p;

@@ -130,6 +130,16 @@ struct TuneTable {
     return Geo{0, 0};
   }
   int64_t max_serve_states() const { return (int64_t)kServeWaves * kWave * 16; }
+  // Serving across several resident workgroups (multi-workgroup layout):
+  // 4 states per lane where the top segment can hold S-1 and S-2, else 6 or
+  // 8; up to kServeMaxParts workgroups of 16 waves.
+  Geo pick_serve_parts(int S) const {
+    for (int M : {4, 6, 8}) {
+      const int W = (S + kWave * M - 1) / (kWave * M);
+      if (W <= kServeWaves * kServeMaxParts && geo_ok(S, W, M)) return Geo{W, M};
+    }
+    return Geo{0, 0};
+  }
 
   // Largest trellis for the pack kernel: every S up to 4 * 64 * 16 has a
   // pack layout (W <= 4 covers them all; W = 8 layouts leave gaps above).

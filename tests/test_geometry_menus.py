@@ -64,3 +64,15 @@ def test_serve_menu_covers_large_requests():
     strict = [S for S in range(4097, 16385, 2)
               if not any(geo_ok(S, -(-S // (64 * M)), M) and -(-S // (64 * M)) <= 16 for M in pack)]
     assert strict == [14337, 15361]
+
+
+def test_serve_parts_menu():
+    # large served requests may run over up to 4 resident workgroups of 16
+    # waves with 4, 6 or 8 states per lane (the first M whose top segment
+    # holds S-1 and S-2); sizes none of them fits keep the one-workgroup
+    # layout, which covers every size (test above)
+    parts = [4, 6, 8]
+    none = [S for S in range(4097, 16385, 2)
+            if not any(geo_ok(S, -(-S // (64 * M)), M) and -(-S // (64 * M)) <= 64 for M in parts)]
+    assert all((S - 1) % 1536 == 0 for S in none)
+    assert len(none) <= 8

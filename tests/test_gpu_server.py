@@ -172,3 +172,44 @@ def test_server_restarts_after_idle():
         res[i] = srv.wait(t)
     srv.close()
     assert _check(utts, bufs, res) == []
+
+
+def test_server_multi_workgroup_parts():
+    # large requests run over several resident workgroups while a sync
+    # region is free and on one workgroup otherwise: a burst larger than the
+    # region pool takes both layouts, and a long run of one-at-a-time
+    # requests takes one region through all its generations and its reset
+    import paper_2310_17864_amd as ca
+    torch, dev = torch_dev()
+    big = synth.utterance(np.random.default_rng(31), 20000, 32, 4000, 0, 6.0, 1.0, None)
+    st_o, p_o, s_o, _ = oracle.align_f32(big.emission, big.labels, 0)
+    em = torch.from_numpy(big.emission).to(dev)
+    lab = torch.from_numpy(big.labels).to(dev)
+    outs = [(torch.full((big.T,), -7, dtype=torch.int32, device=dev),
+             torch.empty(big.T, dtype=torch.float32, device=dev)) for _ in range(12)]
+    torch.cuda.synchronize()
+    srv = ca.Server(64 << 30)
+    ts = [srv.submit(em, lab, p, s, None, 0) for p, s in outs]
+    res = [srv.wait(t) for t in ts]
+    assert all(r[0] == st_o for r in res)
+    for p, s in outs:
+        assert same_bits(p.cpu().numpy(), p_o) and same_bits(s.cpu().numpy(), s_o)
+
+    small = synth.utterance(np.random.default_rng(32), 2400, 32, 2100, 0, 6.0, 1.0, None)
+    st2, p2, s2, _ = oracle.align_f32(small.emission, small.labels, 0)
+    em2 = torch.from_numpy(small.emission).to(dev)
+    lab2 = torch.from_numpy(small.labels).to(dev)
+    n = 1100                                    # > 1023 generations of one region
+    paths = torch.full((n, small.T), -7, dtype=torch.int32, device=dev)
+    scs = torch.empty((n, small.T), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    sts = []
+    for i in range(n):                          # one at a time: region 0 each time
+        sts.append(srv.wait(srv.submit(em2, lab2, paths[i], scs[i], None, 0))[0])
+    assert sts == [st2] * n
+    ref_p = torch.from_numpy(p2).to(dev)
+    ref_s = torch.from_numpy(s2.view(np.int32)).to(dev)
+    bad = int((paths != ref_p).any(dim=1).sum().item()) + \
+        int((scs.view(torch.int32) != ref_s).any(dim=1).sum().item())
+    srv.close()
+    assert bad == 0
