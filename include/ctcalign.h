@@ -230,7 +230,9 @@ typedef struct ctcalign_timing {
 } ctcalign_timing;
 
 typedef struct ctcalign_server_stats {
-  uint64_t submitted, completed, launches, timeouts;
+  uint64_t submitted, completed;
+  uint64_t launches;         /* admitted groups handed to the resident kernel */
+  uint64_t timeouts;         /* groups the watchdog gave up on */
   size_t peak_charge_bytes;  /* largest sum of charges in flight */
   size_t budget_bytes;
   int32_t peak_inflight, waiting, inflight;

@@ -213,3 +213,33 @@ def test_server_multi_workgroup_parts():
         int((scs.view(torch.int32) != ref_s).any(dim=1).sum().item())
     srv.close()
     assert bad == 0
+
+
+def test_server_padded_large_requests():
+    # rows the kernels cannot stage directly (C not 32/256, or a misaligned
+    # emission pointer) are padded by the workgroup that runs the request,
+    # here on the one-workgroup layout of a large trellis
+    import paper_2310_17864_amd as ca
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(41)
+    u1 = synth.utterance(rng, 12000, 100, 2500, 3, 6.0, 1.0, None)          # C = 100, blank 3
+    u2 = synth.utterance(rng, 9000, 32, 1800, 0, 6.0, 1.0, None)            # misaligned rows
+    flat = torch.zeros(u2.T * u2.C + 1, dtype=torch.float32, device=dev)
+    flat[1:] = torch.from_numpy(u2.emission.reshape(-1)).to(dev)
+    em2 = flat[1:].view(u2.T, u2.C)                                           # 4-byte offset
+    outs = []
+    srv = ca.Server(64 << 30)
+    tickets = []
+    for u, em in ((u1, torch.from_numpy(u1.emission).to(dev)), (u2, em2)):
+        lab = torch.from_numpy(u.labels).to(dev)
+        p = torch.full((u.T,), -7, dtype=torch.int32, device=dev)
+        s = torch.empty(u.T, dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        outs.append((u, em, lab, p, s))
+        tickets.append(srv.submit(em, lab, p, s, None, u.blank))
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    for (u, _, _, p, s), (st, _) in zip(outs, res):
+        st_o, p_o, s_o, _ = oracle.align_f32(u.emission, u.labels, u.blank)
+        assert st == st_o
+        assert same_bits(p.cpu().numpy(), p_o) and same_bits(s.cpu().numpy(), s_o)
