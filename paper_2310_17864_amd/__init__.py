@@ -246,11 +246,13 @@ class Plan:
 class Server:
     """Continuous-batching alignment server on one device.
 
-    submit() queues a request whose tensors stay on the device; the library's
-    worker thread admits requests in arrival order while their backpointer
-    memory fits `budget_bytes`, launches each admitted group, and overlaps it
-    with the groups already running.  wait()/poll() return (status, timing)
-    with timing = (submit, admit, launch, done) on the monotonic clock.
+    submit() queues a request whose tensors stay on the device (written before
+    the call); the library's worker thread admits requests in arrival order
+    while their backpointer memory fits `budget_bytes` and hands each admitted
+    group to a resident kernel, where it runs beside the requests admitted
+    before it; each request completes on its own.  wait()/poll() return
+    (status, timing) with timing = (submit, admit, launch, done) on the
+    monotonic clock (launch: handed to the device).
     """
 
     def __init__(self, budget_bytes: int, max_inflight: int = 4096, ctx: Optional[Context] = None,
