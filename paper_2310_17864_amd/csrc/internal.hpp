@@ -87,7 +87,8 @@ struct PadDesc {
 // and stores to it (no read-modify-write), so there is no cross-workgroup
 // atomic on the device at all.
 constexpr int kServeWaves = 16;
-constexpr int kServeMaxParts = 4;   // workgroups one served alignment may span
+constexpr int kServeMaxParts = 8;   // workgroups one served alignment may span
+constexpr int kServePartWaves = 8;  // segments per workgroup of such an alignment (2 waves per SIMD)
 enum : int32_t {
   kItemSegments = 0,   // waves run segments of the item's alignments (which/seg/first)
   kItemPart = 1,       // part `part` of `nparts` of inst[0] in the multi-workgroup layout
@@ -103,7 +104,7 @@ struct ServeItem {                // one workgroup's work: up to 16 segments
   PadDesc pad;
   XSync* xs;                      // kItemPart / kItemReset: the sync region
   uint32_t xtag;                  // kItemPart: the generation tag of this alignment
-  int16_t part, nparts;           // kItemPart: segments 16*part .. 16*part+15
+  int16_t part, nparts;           // kItemPart: segments 8*part .. 8*part+7
 };
 static_assert(sizeof(ServeItem) % 8 == 0, "items are copied in 8-byte words");
 struct ServeBox {                 // per resident workgroup b (host memory)

@@ -387,12 +387,16 @@ k_serve(const ServeItem* items, ServeBox* box, const int32_t* stop, uint64_t epo
       const int part = __builtin_amdgcn_readfirstlane((int)it->part);
       XSync* xs = it->xs;
       const uint32_t tag = (uint32_t)__builtin_amdgcn_readfirstlane((int)it->xtag);
+      // 8 segments per workgroup (2 waves per SIMD: the chain's frames stay
+      // short); waves 8..15 idle
       const Ring r{ring[w]};
-      switch (in.M) {
-        case 4: run_multi<4, kServeWaves>(in, xs, tag, sy, r, part, w, lane, bad); break;
-        case 6: run_multi<6, kServeWaves>(in, xs, tag, sy, r, part, w, lane, bad); break;
-        case 8: run_multi<8, kServeWaves>(in, xs, tag, sy, r, part, w, lane, bad); break;
-        default: break;
+      if (w < kServePartWaves) {
+        switch (in.M) {
+          case 4: run_multi<4, kServePartWaves>(in, xs, tag, sy, r, part, w, lane, bad); break;
+          case 6: run_multi<6, kServePartWaves>(in, xs, tag, sy, r, part, w, lane, bad); break;
+          case 8: run_multi<8, kServePartWaves>(in, xs, tag, sy, r, part, w, lane, bad); break;
+          default: break;
+        }
       }
     } else if (__builtin_amdgcn_readfirstlane(it->npad)) {
       // emission rows into the compiled stride (zeros in the pad columns)
@@ -629,7 +633,7 @@ bool geometry_supported_serve(int W, int M) {
 
 static const int kServePartMenu[] = {4, 6, 8};
 bool geometry_supported_serve_parts(int W, int M) {
-  return W > 0 && W <= kServeWaves * kServeMaxParts && W <= kXWaves * kXMaxGroups &&
+  return W > 0 && W <= kServePartWaves * kServeMaxParts && W <= kXWaves * kXMaxGroups &&
          m_in(M, kServePartMenu, 3);
 }
 

@@ -34,7 +34,8 @@ int persistent_blocks_per_cu();
 hipError_t launch_serve(const ServeItem* d_items, ServeBox* d_box, const int32_t* d_stop,
                         uint64_t epoch, int64_t idle_limit, int grid, hipStream_t st);
 bool geometry_supported_serve(int W, int M);
-// the serving kernel's multi-workgroup parts: W <= 64 segments, M in {4, 6, 8}
+// the serving kernel's multi-workgroup parts: W <= 64 segments (8 per
+// workgroup), M in {4, 6, 8}
 bool geometry_supported_serve_parts(int W, int M);
 
 }  // namespace ctca

@@ -169,7 +169,7 @@ class ServeExec {
         ++rg.gen;
         flag_region_[f] = r;
         const Inst in = make_inst(*p, p->gp, reqs[k]->arena_off, d_flag_ + f);
-        const int nparts = (in.W + kServeWaves - 1) / kServeWaves;
+        const int nparts = (in.W + kServePartWaves - 1) / kServePartWaves;
         for (int part = 0; part < nparts; ++part) {
           ServeItem it = blank_item();
           it.kind = kItemPart;

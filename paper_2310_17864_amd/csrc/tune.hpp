@@ -132,11 +132,11 @@ struct TuneTable {
   int64_t max_serve_states() const { return (int64_t)kServeWaves * kWave * 16; }
   // Serving across several resident workgroups (multi-workgroup layout):
   // 4 states per lane where the top segment can hold S-1 and S-2, else 6 or
-  // 8; up to kServeMaxParts workgroups of 16 waves.
+  // 8; up to kServeMaxParts workgroups running 8 segments each.
   Geo pick_serve_parts(int S) const {
     for (int M : {4, 6, 8}) {
       const int W = (S + kWave * M - 1) / (kWave * M);
-      if (W <= kServeWaves * kServeMaxParts && geo_ok(S, W, M)) return Geo{W, M};
+      if (W <= kServePartWaves * kServeMaxParts && geo_ok(S, W, M)) return Geo{W, M};
     }
     return Geo{0, 0};
   }
