@@ -244,11 +244,13 @@ typedef struct ctcalign_server_stats {
  * against bp_budget_bytes; requests are admitted in arrival order (FIFO)
  * while the charge in flight stays within the budget and fewer than
  * max_inflight requests are on the device.  Admitted requests run on a
- * resident kernel (one 16-wave workgroup per compute unit) that the server
- * keeps on its own stream while there is work and stops about 20 ms after
- * the last request; each request completes on its own, as soon as its
- * alignment is written.  While that kernel is resident, kernels the caller
- * queues on a stream that shares its hardware queue wait for it to stop.
+ * resident kernel (one 16-wave workgroup per compute unit, or as many as
+ * $CTCALIGN_SERVE_WGS says) that the server keeps on its own stream while
+ * there is work and stops about 20 ms after the last request; each request
+ * completes on its own, as soon as its alignment is written.  While that
+ * kernel is resident it holds the compute units it runs on: other kernels
+ * (and kernels the caller queues on a stream sharing its hardware queue)
+ * wait for it to stop.
  * Requests hold up to S = 2L+1 = 16384 states.
  * Errors: EINVAL, ENOMEM (arena or pinned host memory), EDEVICE. */
 int ctcalign_server_create(ctcalign_ctx *ctx, size_t bp_budget_bytes, int32_t max_inflight,

@@ -101,7 +101,14 @@ class ServeExec {
   ServeExec(ctcalign_ctx* ctx, char* arena) : ctx_(ctx), arena_(arena) {}
 
   int init() {
+    // one resident workgroup per CU holds the whole device while it runs;
+    // CTCALIGN_SERVE_WGS keeps it to fewer CUs (the rest stay free for
+    // other kernels)
     grid_ = std::max(ctx_->num_cu, 1);
+    if (const char* v = std::getenv("CTCALIGN_SERVE_WGS")) {
+      const int n = std::atoi(v);
+      if (n >= 1 && n < grid_) grid_ = n;
+    }
     if (ctx_->device < 0 || ctx_->device >= kMaxDev) return CTCALIGN_EDEVICE;
     HIP_TRY(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&ended_, hipEventDisableTiming));
@@ -160,7 +167,8 @@ class ServeExec {
       free_flag_.pop_back();
       __atomic_store_n(h_flag_ + f, -1, __ATOMIC_RELEASE);
       h.flag[k] = f;
-      const int r = p->gp.W > 0 ? free_region() : -1;
+      const bool fits = (p->gp.W + kServePartWaves - 1) / kServePartWaves <= grid_;
+      const int r = p->gp.W > 0 && fits ? free_region() : -1;
       if (r >= 0) {
         // over several resident workgroups, tagged with the region's next
         // generation

@@ -243,3 +243,15 @@ def test_server_padded_large_requests():
         st_o, p_o, s_o, _ = oracle.align_f32(u.emission, u.labels, u.blank)
         assert st == st_o
         assert same_bits(p.cpu().numpy(), p_o) and same_bits(s.cpu().numpy(), s_o)
+
+
+def test_server_on_few_workgroups(monkeypatch):
+    # the resident kernel kept to 2 workgroups: requests queue for them, large
+    # ones whose parts would need more workgroups take the one-workgroup
+    # layout, and every result still matches the oracle
+    monkeypatch.setenv("CTCALIGN_SERVE_WGS", "2")
+    utts = _pool()
+    bufs = _upload(utts)
+    res, stats = _serve(utts, bufs, 64 << 30)
+    assert _check(utts, bufs, res) == []
+    assert stats["completed"] == len(utts)
