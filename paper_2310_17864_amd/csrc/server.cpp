@@ -483,9 +483,10 @@ void worker_loop(ctcalign_server* s) {
       // the kernel idles on the device: look again before stopping it
       s->cv_work.wait_for(lk, std::chrono::milliseconds(1));
     } else {
-      // requests in flight: poll their flags every few microseconds
+      // requests in flight: poll their flags every few microseconds (a timed
+      // sleep would last the kernel's timer slack, ~50 us)
       lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(10));
+      for (int i = 0; i < 16; ++i) std::this_thread::yield();
       lk.lock();
     }
   }
