@@ -117,6 +117,8 @@ class ServeExec {
         (rc = host_alloc(&h_stop_, &d_stop_, 16)) || (rc = host_alloc(&h_flag_, &d_flag_, kFlags)))
       return rc;
     sent_.assign(grid_, 0);
+    busy_.assign(grid_, 0);
+    idle_since_.assign(grid_, 0.0);
     reset_of_.assign(grid_, -1);
     flag_region_.assign(kFlags, -1);
     free_flag_.reserve(kFlags);
@@ -295,13 +297,20 @@ class ServeExec {
       last_work_ = mono_now();
     }
     if (!running_ || stopping_) return;
-    // idle workgroups (round robin from rr_); a finished reset frees its region
+    // idle workgroups, most recently finished first: those still poll their
+    // mailbox often (a workgroup backs off the longer it idles); a finished
+    // reset frees its region
     std::vector<int> idle;
+    const double now = mono_now();
     for (int n = 0; n < grid_; ++n) {
       const int b = (rr_ + n) % grid_;
       const uint64_t live = __atomic_load_n(&h_box_[b].live, __ATOMIC_ACQUIRE);
       const uint64_t ack = __atomic_load_n(&h_box_[b].ack, __ATOMIC_ACQUIRE);
       if (ack != sent_[b]) continue;
+      if (busy_[b]) {
+        busy_[b] = 0;
+        idle_since_[b] = now;
+      }
       if (reset_of_[b] >= 0) {
         regions_[reset_of_[b]].gen = 0;
         regions_[reset_of_[b]].resetting = false;
@@ -309,6 +318,8 @@ class ServeExec {
       }
       if (live == epoch_) idle.push_back(b);
     }
+    std::stable_sort(idle.begin(), idle.end(),
+                     [&](int a, int b) { return idle_since_[a] > idle_since_[b]; });
     // hand out items in order; the parts of one alignment go out together
     // (they wait on each other), or not at all this round
     size_t next = 0;
@@ -320,6 +331,7 @@ class ServeExec {
       for (size_t u = 0; u < unit; ++u) {
         const int b = idle[next++];
         rr_ = (b + 1) % grid_;
+        busy_[b] = 1;
         const ServeItem& it = pending_.front();
         if (it.kind == kItemReset) reset_of_[b] = region_of(it.xs);
         std::memcpy((void*)&h_items_[b], &it, sizeof(ServeItem));
@@ -438,6 +450,8 @@ class ServeExec {
   std::deque<ServeItem> pending_;    // items waiting for an idle workgroup
   std::vector<Region> regions_;
   std::vector<int> reset_of_;        // per workgroup: region its unacknowledged reset item clears
+  std::vector<char> busy_;           // per workgroup: an item posted, not yet seen acknowledged
+  std::vector<double> idle_since_;   // per workgroup: when its last item was seen acknowledged
   std::vector<int> flag_region_;     // per completion flag: region its alignment uses
   uint64_t epoch_ = 0;
   int rr_ = 0;
