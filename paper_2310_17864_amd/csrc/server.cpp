@@ -18,6 +18,7 @@
 // reused) without waiting for anything else.  The kernel is stopped after a
 // short idle period and started again when work arrives.
 #include <hip/hip_runtime.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <atomic>
@@ -482,6 +483,8 @@ namespace {
 
 void worker_loop(ctcalign_server* s) {
   (void)hipSetDevice(s->ctx->device);
+  // short sleeps while requests are in flight (the default slack is ~50 us)
+  (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     if (s->stop && s->sched->idle()) break;
@@ -497,10 +500,11 @@ void worker_loop(ctcalign_server* s) {
       // the kernel idles on the device: look again before stopping it
       s->cv_work.wait_for(lk, std::chrono::milliseconds(1));
     } else {
-      // requests in flight: poll their flags every few microseconds (a timed
-      // sleep would last the kernel's timer slack, ~50 us)
+      // requests in flight: poll their flags every ~10 us (this thread's
+      // timer slack is set to 1 us; a spin here would keep submitting
+      // threads from the lock)
       lk.unlock();
-      for (int i = 0; i < 16; ++i) std::this_thread::yield();
+      std::this_thread::sleep_for(std::chrono::microseconds(10));
       lk.lock();
     }
   }
