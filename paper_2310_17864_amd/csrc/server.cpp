@@ -43,7 +43,7 @@ constexpr int kMaxBatch = 1024;       // requests per admitted group
 constexpr int kFlags = 1 << 16;       // completion flags (requests in flight)
 constexpr double kIdleStop = 0.02;    // seconds without work before the kernel is stopped
 constexpr int64_t kDeviceIdle = 1000000000;  // a workgroup's own idle limit: 10 s of the 100 MHz clock
-constexpr int kRegions = 8;           // sync regions: large alignments spread over workgroups at once
+constexpr int kRegions = 16;          // sync regions: large alignments spread over workgroups at once
 constexpr int kMaxDev = 64;
 
 struct Payload {
