@@ -7,6 +7,8 @@
 namespace ctca {
 
 bool geometry_supported_one(int W, int M);
+// single-workgroup layouts only (k_one, k_one_long)
+bool geometry_supported_one_wg(int W, int M);
 bool geometry_supported_pack(int W, int M);
 hipError_t launch_one(const Inst& in, hipStream_t st);
 // one long alignment over ceil(W/8) workgroups; xs: its sync region, gen:

@@ -23,7 +23,7 @@ import statistics
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["engine.hpp", "internal.hpp", "kernels.hip", "tune.hpp", "api.cpp"]
+KERNEL_SOURCES = ["engine.hpp", "internal.hpp", "kernels_common.hpp", "k_batch.hip", "tune.hpp", "api.cpp"]
 
 
 def kernel_source_hash() -> str:
