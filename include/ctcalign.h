@@ -89,8 +89,12 @@ int ctcalign_ctx_create(int device, ctcalign_ctx **ctx);
 int ctcalign_ctx_destroy(ctcalign_ctx *ctx);
 
 /* Bytes of backpointer workspace one alignment of shape (T, L, C) needs under
- * the geometry this context would pick; 0 on invalid shape.  Depends on the
- * tuning table: query again after ctcalign_tune. */
+ * the geometry this context would pick; 0 on invalid shape.  The backtrack of
+ * the Viterbi recursion (paper Sec. 4, "CTC-based forced alignment") needs
+ * the choice made at every state and frame: 1.5 bits per state and frame
+ * here, laid out per wavefront, so the size depends on the geometry (W, M)
+ * and therefore on the context's tuning table and on C, not on (T, L) alone.
+ * Query again after ctcalign_tune_set / _load. */
 size_t ctcalign_workspace_bytes(ctcalign_ctx *ctx, int32_t T, int32_t L, int32_t C);
 
 /* ---- geometry tuning ------------------------------------------------------
@@ -118,18 +122,24 @@ int ctcalign_tune_load(ctcalign_ctx *ctx, const char *path);
 
 /* ---- one utterance ------------------------------------------------------ */
 
-/* Aligns one utterance on the default context (created on first use on the
- * current device) and its stream, and waits for the result.
+/* Forced alignment of one utterance (paper Sec. 4, "CTC-based forced
+ * alignment": the frame-level alignment of a transcript to a CTC model's
+ * outputs; the recurrence above).  Runs on the default context (created on
+ * first use on the current device) and its stream, and waits for the result.
  * Returns OK, EINVAL, EINFEASIBLE (device-side outcome), ENOMEM or EDEVICE. */
 int ctcalign_align(const float *emission, int32_t T, int32_t C,
                    const int32_t *labels, int32_t L, int32_t blank,
                    int32_t *out_path, float *out_scores);
 
-/* Asynchronous single alignment on `stream` (NULL: HIP's null stream).
+/* The same alignment (paper Sec. 4, "CTC-based forced alignment"),
+ * asynchronous on `stream` (NULL: HIP's null stream).
  * out_total (device, 1 float) and out_status (device, 1 int32) may be NULL.
  * workspace (device, >= ctcalign_workspace_bytes, 256-byte aligned) may be
- * NULL: the context's arena is used (then calls on one context serialise on
- * its arena).  Returns OK when the launch was queued; the alignment's own
+ * NULL: the context's arena is used.  Calls that use the context's arena, or
+ * its buffer for re-laid-out emission rows (C not 32 or 256, or a pointer
+ * not 16-byte aligned), are ordered after the previous such call even when
+ * they come on different streams (the stream waits for an event the last
+ * one recorded).  Returns OK when the launch was queued; the alignment's own
  * status is written to *out_status.
  * Trellises above 4096 states run over several workgroups that exchange
  * boundary values through a per-device sync region: such launches are
@@ -142,7 +152,11 @@ int ctcalign_align_ex(ctcalign_ctx *ctx, const float *emission, int32_t T, int32
                       int32_t *out_status, void *workspace, size_t ws_bytes,
                       ctcalign_stream stream);
 
-/* Token spans of an alignment (device pointers; asynchronous on `stream`):
+/* Token spans of an alignment: the frame-level path (paper Sec. 4,
+ * "CTC-based forced alignment") grouped into one segment per transcript
+ * token, the step that turns a frame alignment into token time stamps for
+ * segmentation (the method the paper cites there, Kuerzinger et al. 2020,
+ * CTC segmentation).  Device pointers; asynchronous on `stream`:
  * each maximal run of frames with the same non-blank class is one span --
  * one per transcript token, since equal neighbouring tokens are separated by
  * a blank in any CTC alignment.  For span i (in frame order): out_token[i]
@@ -157,7 +171,10 @@ int ctcalign_token_spans(const int32_t *path, const float *scores, int32_t T, in
 
 /* ---- many utterances: one persistent kernel over a device work queue ---- */
 
-/* Builds a plan for N utterances packed in flat device arrays.  Host arrays
+/* Builds a plan that aligns N utterances, each exactly as ctcalign_align_ex
+ * would (paper Sec. 4, "CTC-based forced alignment"; the paper describes no
+ * batching, this is a throughput layout of the same computation), packed in
+ * flat device arrays.  Host arrays
  * (length N): em_off (element offset of each [T_i][C_i] emission in
  * `emissions`), T, C, lab_off (element offset in `labels`), L, frame_off
  * (element offset of each utterance's T_i outputs in out_paths/out_scores).
@@ -182,7 +199,9 @@ int ctcalign_plan_create(ctcalign_ctx *ctx, int32_t N,
                          ctcalign_plan **plan);
 
 /* Replays the plan's graph on `stream` (NULL: HIP's null stream).
- * Asynchronous; per-utterance statuses land in out_status. */
+ * Asynchronous; per-utterance statuses land in out_status.  A replay waits
+ * for the plan's previous replay when that ran on another stream (they share
+ * the plan's workspace). */
 int ctcalign_plan_run(ctcalign_plan *plan, ctcalign_stream stream);
 
 /* Profiling aid: when the plan was created with $CTCALIGN_TRACE=1, copies
@@ -212,7 +231,12 @@ int ctcalign_align_batched(ctcalign_ctx *ctx, int32_t N,
 
 /* One alignment request.  All pointers are device pointers that must stay
  * valid until the request's ticket completes; emission/labels as for
- * ctcalign_align_ex, out_total may be NULL. */
+ * ctcalign_align_ex, out_total may be NULL.  ready_event (a hipEvent_t, or
+ * NULL) is an event the caller recorded on the stream that writes the
+ * emission and labels (and last used the outputs): the request is admitted
+ * only once that event has completed, and requests behind it in the queue
+ * wait with it (FIFO).  The event must stay valid until the ticket
+ * completes.  With NULL the inputs must be written before the submit call. */
 typedef struct ctcalign_request {
   const float *emission;
   int32_t T, C;
@@ -221,6 +245,7 @@ typedef struct ctcalign_request {
   int32_t *out_path;
   float *out_scores;
   float *out_total;
+  void *ready_event;
 } ctcalign_request;
 
 /* Per-request timestamps, seconds on the host's monotonic clock
@@ -233,13 +258,16 @@ typedef struct ctcalign_server_stats {
   uint64_t submitted, completed;
   uint64_t launches;         /* admitted groups handed to the resident kernel */
   uint64_t timeouts;         /* groups the watchdog gave up on */
+  uint64_t readmitted;       /* requests queued again after a watchdog expiry */
   size_t peak_charge_bytes;  /* largest sum of charges in flight */
   size_t budget_bytes;
   int32_t peak_inflight, waiting, inflight;
   int32_t budget_violated;   /* 1 if the in-flight charge ever exceeded the budget */
 } ctcalign_server_stats;
 
-/* Starts a server on the context's device.  Each request is charged its
+/* Starts a server on the context's device that runs alignments (paper
+ * Sec. 4, "CTC-based forced alignment"; each request's result is bitwise
+ * the one ctcalign_align_ex gives) as they arrive.  Each request is charged its
  * backpointer memory, T*(2L+1)/4 bytes (or its actual workspace if larger),
  * against bp_budget_bytes; requests are admitted in arrival order (FIFO)
  * while the charge in flight stays within the budget and fewer than
@@ -256,11 +284,11 @@ typedef struct ctcalign_server_stats {
 int ctcalign_server_create(ctcalign_ctx *ctx, size_t bp_budget_bytes, int32_t max_inflight,
                            ctcalign_server **server);
 
-/* Queues a request (never blocks).  *ticket identifies it.  The emission and
- * labels must be written, and no other work may write the outputs, before
- * the call (the request may start at once).  Errors: EINVAL (bad arguments
- * or 2L+1 > 16384; the request is not queued), ENOMEM (its charge alone
- * exceeds the budget), EAGAIN (queue full). */
+/* Queues a request (never blocks).  *ticket identifies it.  Without a
+ * ready_event the emission and labels must be written, and no other work may
+ * write the outputs, before the call (the request may start at once).
+ * Errors: EINVAL (bad arguments or 2L+1 > 16384; the request is not queued),
+ * ENOMEM (its charge alone exceeds the budget), EAGAIN (queue full). */
 int ctcalign_server_submit(ctcalign_server *server, const ctcalign_request *req, uint64_t *ticket);
 
 /* Non-blocking completion check.  EBUSY while pending; OK once done, with

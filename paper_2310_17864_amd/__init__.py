@@ -13,7 +13,10 @@ per-frame log-probabilities, with per-frame label ids and scores.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import sys
+import weakref
 from typing import Dict, List, Optional, Sequence
 
 import numpy as np
@@ -27,6 +30,31 @@ __all__ = ["align", "token_spans", "align_many_launches", "Context", "Plan", "Se
            "EDEVICE", "EAGAIN", "EBUSY"]
 
 _contexts: Dict[int, "Context"] = {}
+
+# Live library objects, closed in dependency order (servers, then plans, then
+# contexts) by an exit hook that runs while the HIP runtime is still up.
+# After it has run -- or once the interpreter is finalizing -- close() and
+# __del__ make no library call at all.
+_live = {"server": weakref.WeakSet(), "plan": weakref.WeakSet(), "context": weakref.WeakSet()}
+_closed_at_exit = False
+
+
+def _library_usable() -> bool:
+    return not _closed_at_exit and not sys.is_finalizing()
+
+
+@atexit.register
+def _close_all_at_exit():
+    global _closed_at_exit
+    for kind in ("server", "plan", "context"):
+        for obj in list(_live[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+    _contexts.clear()
+    _closed_at_exit = True
+
 
 PACK_WAVES = 4   # wavefronts per work item of the batched kernel
 
@@ -50,10 +78,12 @@ class Context:
         _lib.check(lib.ctcalign_ctx_create(int(device), ctypes.byref(h)), "ctx_create")
         self.handle = h
         self.device = int(device)
+        _live["context"].add(self)
 
     def close(self):
         if getattr(self, "handle", None):
-            _lib.load().ctcalign_ctx_destroy(self.handle)
+            if _library_usable():
+                _lib.load().ctcalign_ctx_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -213,6 +243,7 @@ class Plan:
             self.totals.data_ptr(), self.status.data_ptr(), ctypes.byref(handle))
         _lib.check(rc, "plan_create")
         self.handle = handle
+        _live["plan"].add(self)
 
     def run(self, stream=None):
         torch = _torch()
@@ -233,7 +264,8 @@ class Plan:
 
     def close(self):
         if getattr(self, "handle", None):
-            _lib.load().ctcalign_plan_destroy(self.handle)
+            if _library_usable():
+                _lib.load().ctcalign_plan_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -264,17 +296,25 @@ class Server:
                    "server_create")
         self.handle = h
         self._keep = {}
+        _live["server"].add(self)
 
     def submit(self, emission, labels, out_path, out_scores, out_total=None, blank: int = 0) -> int:
+        """Queues one alignment.  An event recorded on the current stream goes
+        with the request: the server admits it only once the work queued so
+        far on that stream (which writes the emission and labels) is done."""
+        torch = _torch()
         T, C = emission.shape
         L = labels.numel()
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(emission.device))
         req = _lib.Request(emission.data_ptr(), T, C, labels.data_ptr() if L else None, L, blank,
                            out_path.data_ptr(), out_scores.data_ptr(),
-                           out_total.data_ptr() if out_total is not None else None)
+                           out_total.data_ptr() if out_total is not None else None,
+                           ev.cuda_event)
         t = ctypes.c_uint64()
         _lib.check(_lib.load().ctcalign_server_submit(self.handle, ctypes.byref(req),
                                                       ctypes.byref(t)), "server_submit")
-        self._keep[t.value] = (emission, labels, out_path, out_scores, out_total)
+        self._keep[t.value] = (emission, labels, out_path, out_scores, out_total, ev)
         return int(t.value)
 
     def _finish(self, ticket: int, block: bool):
@@ -301,7 +341,8 @@ class Server:
 
     def close(self):
         if getattr(self, "handle", None):
-            _lib.load().ctcalign_server_destroy(self.handle)
+            if _library_usable():
+                _lib.load().ctcalign_server_destroy(self.handle)
             self.handle = None
             self._keep.clear()
 

@@ -22,7 +22,8 @@ SZ = ctypes.c_size_t
 
 class Request(ctypes.Structure):
     _fields_ = [("emission", P), ("T", I32), ("C", I32), ("labels", P), ("L", I32),
-                ("blank", I32), ("out_path", P), ("out_scores", P), ("out_total", P)]
+                ("blank", I32), ("out_path", P), ("out_scores", P), ("out_total", P),
+                ("ready_event", P)]
 
 
 class Timing(ctypes.Structure):
@@ -33,6 +34,7 @@ class Timing(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("launches", ctypes.c_uint64), ("timeouts", ctypes.c_uint64),
+                ("readmitted", ctypes.c_uint64),
                 ("peak_charge_bytes", SZ), ("budget_bytes", SZ), ("peak_inflight", I32),
                 ("waiting", I32), ("inflight", I32), ("budget_violated", I32)]
 

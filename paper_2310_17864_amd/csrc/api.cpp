@@ -109,9 +109,18 @@ int launch_single(ctcalign_ctx* ctx, const float* emission, int32_t T, int32_t C
 
   const size_t need = round_up((size_t)bp_words(T, in.W, in.M) * 4, 256);
   const bool multi = geometry_is_multi(in.W, in.M);
+  if (workspace && (ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255u)))
+    return CTCALIGN_EINVAL;
+  const bool padded = !(C == in.stride && aligned16(emission));
+  // the context's arena and pad buffer are shared across streams: wait for
+  // the last call that used them, and let the next one wait for this one
+  const bool shared = !workspace || padded;
+  if (shared) {
+    if (!ctx->arena_ev) HIP_TRY(hipEventCreateWithFlags(&ctx->arena_ev, hipEventDisableTiming));
+    if (ctx->arena_used && ctx->arena_stream != st) HIP_TRY(hipStreamWaitEvent(st, ctx->arena_ev, 0));
+  }
   char* ws;
   if (workspace) {
-    if (ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255u)) return CTCALIGN_EINVAL;
     ws = static_cast<char*>(workspace);
   } else {
     rc = ctx->ws.reserve(need);
@@ -120,7 +129,7 @@ int launch_single(ctcalign_ctx* ctx, const float* emission, int32_t T, int32_t C
   }
   in.bp = reinterpret_cast<uint32_t*>(ws);
 
-  if (C == in.stride && aligned16(emission)) {
+  if (!padded) {
     in.em = emission;
   } else {
     // re-layout rows to the compiled stride in the context's pad buffer
@@ -131,8 +140,17 @@ int launch_single(ctcalign_ctx* ctx, const float* emission, int32_t T, int32_t C
     in.em = static_cast<float*>(ctx->pad.ptr);
   }
   CTCA_LOG(2, "align T=%d C=%d L=%d -> W=%d M=%d stride=%d", T, C, L, in.W, in.M, in.stride);
-  if (multi) return launch_multi_serial(ctx->device, in, st);
-  HIP_TRY(launch_one(in, st));
+  if (multi) {
+    rc = launch_multi_serial(ctx->device, in, st);
+    if (rc) return rc;
+  } else {
+    HIP_TRY(launch_one(in, st));
+  }
+  if (shared) {
+    HIP_TRY(hipEventRecord(ctx->arena_ev, st));
+    ctx->arena_stream = st;
+    ctx->arena_used = true;
+  }
   return CTCALIGN_OK;
 }
 
@@ -268,6 +286,7 @@ int ctcalign_ctx_destroy(ctcalign_ctx* c) {
   if (c->cached) ctcalign_plan_destroy(c->cached);
   c->ws.release();
   c->pad.release();
+  if (c->arena_ev) (void)hipEventDestroy(c->arena_ev);
   if (c->h_status) (void)hipHostFree(c->h_status);
   if (c->d_status) (void)hipFree(c->d_status);
   if (c->d_total) (void)hipFree(c->d_total);
@@ -599,7 +618,13 @@ int ctcalign_plan_create(ctcalign_ctx* ctx, int32_t N, const float* emissions,
 int ctcalign_plan_run(ctcalign_plan* p, ctcalign_stream stream) {
   if (!p) return CTCALIGN_EINVAL;
   HIP_TRY(hipSetDevice(p->ctx->device));
-  HIP_TRY(hipGraphLaunch(p->exec, static_cast<hipStream_t>(stream)));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!p->run_ev) HIP_TRY(hipEventCreateWithFlags(&p->run_ev, hipEventDisableTiming));
+  if (p->ran && p->run_stream != st) HIP_TRY(hipStreamWaitEvent(st, p->run_ev, 0));
+  HIP_TRY(hipGraphLaunch(p->exec, st));
+  HIP_TRY(hipEventRecord(p->run_ev, st));
+  p->run_stream = st;
+  p->ran = true;
   return CTCALIGN_OK;
 }
 
@@ -639,6 +664,7 @@ int ctcalign_plan_destroy(ctcalign_plan* p) {
   if (p->crit_stream) (void)hipStreamDestroy(p->crit_stream);
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
   if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  if (p->run_ev) (void)hipEventDestroy(p->run_ev);
   if (p->ctx && p->ctx->cached == p) p->ctx->cached = nullptr;
   delete p;
   return CTCALIGN_OK;

@@ -86,6 +86,12 @@ struct ctcalign_ctx {
   int num_cu = 0;
   ctca::Arena ws;  // backpointer workspace for single alignments
   ctca::Arena pad; // padded emission copies for single alignments
+  // ws and pad are shared by every call that brings no workspace of its own,
+  // whatever stream it comes on: each such call waits for the previous one
+  // (an event recorded on that call's stream) before it touches them
+  hipEvent_t arena_ev = nullptr;
+  hipStream_t arena_stream = nullptr;
+  bool arena_used = false;
   int32_t* h_status = nullptr;   // pinned
   int32_t* d_status = nullptr;
   float* d_total = nullptr;
@@ -119,5 +125,10 @@ struct ctcalign_plan {
   int* d_crit = nullptr;
   hipStream_t crit_stream = nullptr;   // capture-time only
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // a replay on one stream waits for the last replay on another one: they
+  // share the backpointer workspace and the queue heads
+  hipEvent_t run_ev = nullptr;
+  hipStream_t run_stream = nullptr;
+  bool ran = false;
   std::vector<int> pack_order_inst;    // first instance of each pack (host copy, for traces)
 };

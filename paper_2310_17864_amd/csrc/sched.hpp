@@ -10,9 +10,11 @@
 // launch.
 //
 // Admission is strictly FIFO: the oldest waiting request is admitted as soon
-// as (a) fewer than max_inflight requests are on the device, (b) its charge
-// fits the budget next to everything in flight, and (c) its workspace fits a
-// free arena range; nothing behind it may overtake it, so nothing starves.
+// as (a) its inputs are ready (the executor says so: e.g. the event its
+// producer recorded has completed), (b) fewer than max_inflight requests are
+// on the device, (c) its charge fits the budget next to everything in
+// flight, and (d) its workspace fits a free arena range; nothing behind it
+// may overtake it, so nothing starves.
 // A request whose charge alone exceeds the budget is refused at submit.
 #pragma once
 #include <stddef.h>
@@ -129,12 +131,14 @@ struct SchedReq {
   size_t ws_bytes = 0;    // bytes taken from the arena
   size_t arena_off = SIZE_MAX;
   int status = -1;        // -1 while pending
+  int retries = 0;        // re-admissions after a watchdog expiry
   double t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
   void* user = nullptr;   // executor payload (descriptor of the alignment)
 };
 
 struct SchedStats {
   uint64_t submitted = 0, completed = 0, launches = 0, timeouts = 0;
+  uint64_t readmitted = 0;        // requests queued again after a watchdog expiry
   size_t peak_charge = 0;
   int peak_inflight = 0;
   bool budget_violated = false;   // stays false: checked on every admission
@@ -143,9 +147,17 @@ struct SchedStats {
 template <class Exec>
 class Scheduler {
  public:
-  Scheduler(Exec* ex, size_t budget, size_t arena_bytes, int max_inflight, double watchdog_s)
+  // A launch that has not finished watchdog_s seconds after it started is
+  // given up on: the executor is told (on_timeout: it may restart its device
+  // side), and each of its unreported requests is queued again at the head of
+  // the FIFO, up to max_retries times (alignment is a pure function of its
+  // inputs, so running it again is safe), then reported as EDEVICE.  The
+  // launch keeps the memory of its requests until the executor reports them
+  // done; a re-admitted request takes memory of its own.
+  Scheduler(Exec* ex, size_t budget, size_t arena_bytes, int max_inflight, double watchdog_s,
+            int max_retries = 1)
       : ex_(ex), budget_(budget), arena_(arena_bytes), max_inflight_(max_inflight),
-        watchdog_s_(watchdog_s) {}
+        watchdog_s_(watchdog_s), max_retries_(max_retries) {}
 
   // 0 ok, 3 (ENOMEM) if the request can never fit, 5 (EAGAIN) if the queue is full
   int submit(SchedReq* r, size_t queue_cap) {
@@ -165,6 +177,7 @@ class Scheduler {
     std::vector<SchedReq*> batch;
     while (!fifo_.empty() && ex_->can_launch()) {
       SchedReq* r = fifo_.front();
+      if (!ex_->ready(r)) break;
       if (inflight_reqs_ >= max_inflight_) break;
       if (charge_ + r->charge > budget_) break;
       const size_t off = arena_.alloc(r->ws_bytes);
@@ -185,6 +198,11 @@ class Scheduler {
       for (auto* r : batch) r->t_launch = t;
       Launch L;
       L.reqs = batch;
+      for (auto* r : batch) {
+        L.off.push_back(r->arena_off);
+        L.charge.push_back(r->charge);
+        L.ws.push_back(r->ws_bytes);
+      }
       L.fin.assign(batch.size(), 0);
       L.reported.assign(batch.size(), 0);
       L.t_launch = t;
@@ -205,6 +223,7 @@ class Scheduler {
  private:
   struct Launch {
     std::vector<SchedReq*> reqs;
+    std::vector<size_t> off, charge, ws;   // memory of each request in this launch
     std::vector<char> fin;        // request's memory released
     std::vector<char> reported;   // request handed back (finished or timed out)
     typename Exec::Handle handle;
@@ -212,7 +231,8 @@ class Scheduler {
     bool timed_out = false;
   };
 
-  // Executor contract: poll() fills st[k] with request k's status once it has
+  // Executor contract: ready(r) tells whether request r's inputs may be read
+  // now; poll() fills st[k] with request k's status once it has
   // finished (-1 while it runs) and returns true once the whole launch is
   // over (every st[k] >= 0; its resources may then be released).
   void retire(std::vector<SchedReq*>& done) {
@@ -228,8 +248,8 @@ class Scheduler {
         if (s < 0) continue;
         SchedReq* r = L.reqs[k];
         L.fin[k] = 1;
-        arena_.release(r->arena_off, r->ws_bytes);
-        charge_ -= r->charge;
+        arena_.release(L.off[k], L.ws[k]);
+        charge_ -= L.charge[k];
         inflight_reqs_--;
         if (!L.reported[k]) {
           L.reported[k] = 1;
@@ -244,19 +264,36 @@ class Scheduler {
         launches_.erase(launches_.begin() + i);
         continue;
       }
-      // watchdog: report the requests of a launch that never finishes; their
-      // memory stays reserved until the executor reports them done
+      // watchdog: re-admit (or finally report) the requests of a launch that
+      // does not finish; their memory here stays reserved until the executor
+      // reports them done
       if (!L.timed_out && watchdog_s_ > 0 && t - L.t_launch > watchdog_s_) {
         L.timed_out = true;
         stats_.timeouts++;
+        ex_->on_timeout(L.handle);
+        std::vector<SchedReq*> again;
         for (size_t k = 0; k < L.reqs.size(); ++k) {
           if (L.reported[k]) continue;
           L.reported[k] = 1;
           SchedReq* r = L.reqs[k];
+          if (r->retries < max_retries_) {
+            r->retries++;
+            r->arena_off = SIZE_MAX;
+            stats_.readmitted++;
+            again.push_back(r);
+            continue;
+          }
           r->status = 4;   // EDEVICE
           r->t_done = t;
           done.push_back(r);
           stats_.completed++;
+        }
+        // back into the FIFO at their place in submission order (ahead of
+        // everything submitted after them)
+        for (SchedReq* r : again) {
+          auto pos = fifo_.begin();
+          while (pos != fifo_.end() && (*pos)->t_submit <= r->t_submit) ++pos;
+          fifo_.insert(pos, r);
         }
       }
       ++i;
@@ -268,6 +305,7 @@ class Scheduler {
   ArenaMap arena_;
   int max_inflight_;
   double watchdog_s_;
+  int max_retries_;
   std::deque<SchedReq*> fifo_;
   std::vector<Launch> launches_;
   size_t charge_ = 0;

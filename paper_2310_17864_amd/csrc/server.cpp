@@ -154,6 +154,27 @@ class ServeExec {
 
   int max_batch() const { return kMaxBatch; }
 
+  // the request's producer has finished writing its inputs
+  bool ready(const SchedReq* r) const {
+    const Payload* p = static_cast<const Payload*>(r->user);
+    if (!p->req.ready_event) return true;
+    const hipError_t e = hipEventQuery(static_cast<hipEvent_t>(p->req.ready_event));
+    if (e == hipErrorNotReady) return false;
+    if (e != hipSuccess) CTCA_LOG(1, "server: ready event of ticket %llu: %s",
+                                  (unsigned long long)r->ticket, hipGetErrorString(e));
+    return true;
+  }
+
+  // the watchdog gave up on a launch: stop the resident kernel, so that it
+  // is started again (a new epoch) for the re-admitted requests once it has
+  // ended
+  void on_timeout(Handle&) {
+    if (running_ && !stopping_) {
+      stopping_ = true;
+      __atomic_store_n(h_stop_, 1, __ATOMIC_RELEASE);
+    }
+  }
+
   // room for a whole group: its flags, and a bounded FIFO of items
   bool can_launch() const {
     return (int)free_flag_.size() >= kMaxBatch && (int)pending_.size() < 4 * grid_;
@@ -656,6 +677,7 @@ int ctcalign_server_get_stats(ctcalign_server* s, ctcalign_server_stats* out) {
   out->completed = st.completed;
   out->launches = st.launches;
   out->timeouts = st.timeouts;
+  out->readmitted = st.readmitted;
   out->peak_charge_bytes = st.peak_charge;
   out->budget_bytes = s->budget;
   out->peak_inflight = st.peak_inflight;

@@ -25,7 +25,8 @@ static int failures = 0;
 
 // Completes request k of a launch after lag + ticket % 3 polls (requests of
 // one launch finish at different times); a request with `user` set never
-// completes, nor does its launch.  Tracks the charge on the "device".
+// completes, nor does its launch, and one listed in stuck_once hangs in its
+// first launch only.  Tracks the charge on the "device".
 struct FakeExec {
   struct Handle {
     int polls = 0;
@@ -37,6 +38,11 @@ struct FakeExec {
   size_t device_charge = 0, peak = 0, budget = 0;
   bool violated = false;
   std::vector<uint64_t> admit_order;
+  std::set<uint64_t> not_ready;     // tickets whose inputs are not written yet
+  std::set<uint64_t> stuck_once;    // tickets that hang in their first launch
+  int timeouts_seen = 0;
+  void on_timeout(Handle&) { ++timeouts_seen; }
+  bool ready(const SchedReq* r) const { return not_ready.count(r->ticket) == 0; }
   bool can_launch() const { return launches_open < 8; }
   int max_batch() const { return cap; }
   Handle launch(std::vector<SchedReq*>& reqs) {
@@ -44,7 +50,7 @@ struct FakeExec {
     for (auto* r : reqs) {
       admit_order.push_back(r->ticket);
       device_charge += r->charge;
-      h.stuck.push_back(r->user != nullptr);
+      h.stuck.push_back(r->user != nullptr || (stuck_once.count(r->ticket) && r->retries == 0));
       h.fin.push_back(0);
     }
     peak = std::max(peak, device_charge);
@@ -154,7 +160,7 @@ static void test_watchdog() {
   FakeExec ex;
   ex.budget = 100;
   ex.cap = 1;                       // one request per launch
-  Scheduler<FakeExec> s(&ex, 100, 1 << 16, 10, 0.05);
+  Scheduler<FakeExec> s(&ex, 100, 1 << 16, 10, 0.05, /*max_retries=*/0);
   std::vector<SchedReq> r(3);
   int tag = 1;
   for (int i = 0; i < 3; ++i) {
@@ -187,7 +193,7 @@ static void test_early_completion() {
   ex.budget = 100;
   ex.cap = 2;
   ex.lag = 1;
-  Scheduler<FakeExec> s(&ex, 100, 1 << 16, 10, 0.2);
+  Scheduler<FakeExec> s(&ex, 100, 1 << 16, 10, 0.2, /*max_retries=*/0);
   std::vector<SchedReq> r(3);
   int tag = 1;
   const size_t charge[3] = {50, 40, 50};
@@ -219,6 +225,86 @@ static void test_early_completion() {
   CHECK(s.stats().timeouts == 1);
   CHECK(s.charge_inflight() == 40);
   CHECK(s.stats().completed == 3);
+}
+
+// Watchdog re-admission: a request that hangs in its first launch is queued
+// again at the head of the FIFO (ahead of requests submitted after it), runs
+// to completion in a second launch and reports its own status; one that
+// hangs every time is re-admitted once and then reported as EDEVICE.  Both
+// hung launches keep their memory; the executor hears of every expiry.
+static void test_watchdog_readmits() {
+  FakeExec ex;
+  ex.budget = 1000;
+  ex.cap = 1;
+  Scheduler<FakeExec> s(&ex, 1000, 1 << 16, 10, 0.05, /*max_retries=*/1);
+  std::vector<SchedReq> r(4);
+  int tag = 1;
+  for (int i = 0; i < 4; ++i) {
+    r[i].ticket = 3 * (i + 1);
+    r[i].charge = 10;
+    r[i].ws_bytes = 256;
+  }
+  ex.stuck_once.insert(r[0].ticket);   // hangs once, then runs
+  r[1].user = &tag;                    // hangs every time
+  for (int i = 0; i < 2; ++i) CHECK(s.submit(&r[i], 16) == 0);
+  s.step();
+  s.step();                            // one request per launch
+  CHECK(s.inflight() == 2);
+  std::vector<SchedReq*> fin;
+  const double t0 = mono_now();
+  bool late_submitted = false;
+  while (fin.size() < 4 && mono_now() - t0 < 3.0) {
+    auto f = s.step();
+    fin.insert(fin.end(), f.begin(), f.end());
+    if (!late_submitted && s.stats().timeouts >= 1) {
+      // arrive after the first expiry: must not overtake the re-admitted ones
+      for (int i = 2; i < 4; ++i) CHECK(s.submit(&r[i], 16) == 0);
+      late_submitted = true;
+    }
+    std::this_thread::sleep_for(std::chrono::milliseconds(1));
+  }
+  CHECK(fin.size() == 4);
+  CHECK(r[0].status == 0 && r[0].retries == 1);
+  CHECK(r[1].status == 4 && r[1].retries == 1);
+  CHECK(r[2].status == 0 && r[3].status == 0);
+  CHECK(s.stats().readmitted == 2);
+  CHECK(s.stats().timeouts == 3);      // r0 once, r1 twice
+  CHECK(ex.timeouts_seen == 3);
+  // FIFO across the re-admission: r0 and r1 launched again before r2 and r3
+  std::vector<uint64_t> ord = ex.admit_order;
+  CHECK(ord.size() == 6);
+  if (ord.size() == 6) {
+    CHECK(ord[0] == r[0].ticket && ord[1] == r[1].ticket);
+    CHECK(ord[2] == r[0].ticket && ord[3] == r[1].ticket);
+    CHECK(ord[4] == r[2].ticket && ord[5] == r[3].ticket);
+  }
+  // memory of the hung launches stays reserved: r1's two launches and r0's first
+  CHECK(s.charge_inflight() == 30);
+}
+
+// Requests whose inputs are not ready yet wait at the head of the FIFO and
+// hold back everything behind them; once ready they run in order.
+static void test_ready_gate() {
+  FakeExec ex;
+  ex.budget = 1000;
+  ex.lag = 1;
+  Scheduler<FakeExec> s(&ex, 1000, 1 << 16, 10, 0.0);
+  std::vector<SchedReq> r(3);
+  for (int i = 0; i < 3; ++i) {
+    r[i].ticket = 3 * (i + 1);
+    r[i].charge = 10;
+    r[i].ws_bytes = 256;
+    CHECK(s.submit(&r[i], 16) == 0);
+  }
+  ex.not_ready.insert(r[0].ticket);
+  for (int k = 0; k < 5; ++k) s.step();
+  CHECK(s.inflight() == 0 && s.waiting() == 3);
+  ex.not_ready.clear();
+  int guard = 0;
+  while (!s.idle() && guard++ < 100) s.step();
+  CHECK(s.idle());
+  CHECK(ex.admit_order.size() == 3);
+  for (size_t i = 1; i < ex.admit_order.size(); ++i) CHECK(ex.admit_order[i] > ex.admit_order[i - 1]);
 }
 
 // Pack construction of the server: every alignment gets exactly its W waves,
@@ -295,6 +381,8 @@ int main() {
   test_max_inflight_and_no_overtake();
   test_watchdog();
   test_early_completion();
+  test_watchdog_readmits();
+  test_ready_gate();
   test_pack_by_width();
   test_arena();
   if (failures) {

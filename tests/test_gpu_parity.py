@@ -203,3 +203,18 @@ def test_multi_workgroup_repeated_launches():
         assert np.array_equal(path.cpu().numpy(), p), k
         assert np.array_equal(scores.cpu().numpy().view(np.uint32), s.view(np.uint32)), k
     plan.close()
+
+
+@pytest.mark.slow
+def test_long_form_full_size():
+    # the long-form workload as configured: T = 90,000 frames, C = 32,
+    # L = 15,000 (S = 30,001; 675 MB of 2-bit backpointers), one launch over
+    # several workgroups; paths, scores and total bitwise equal to the float32
+    # oracle, and the float32 total within 1e-3 relative of the float64 one
+    u = synth.cfg_long().utts[0]
+    assert (u.T, u.C, u.L) == (90_000, 32, 15_000)
+    assert compare_one(u.emission, u.labels, 0, "long90000") == []
+    st32, _, _, t32 = oracle.align_f32(u.emission, u.labels, 0)
+    st64, _, _, t64 = oracle.align_f64(u.emission, u.labels, 0)
+    assert st32 == st64 == 0
+    assert abs(float(t32) - float(t64)) <= 1e-3 * abs(float(t64))
