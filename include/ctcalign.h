@@ -152,6 +152,29 @@ int ctcalign_align_ex(ctcalign_ctx *ctx, const float *emission, int32_t T, int32
                       int32_t *out_status, void *workspace, size_t ws_bytes,
                       ctcalign_stream stream);
 
+/* For callers that cannot allocate device memory (work recorded under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * alignment of ctcalign_align_ex, bitwise the same results, asynchronous on
+ * `stream`, with no allocation of any kind during the call.  Backpointers
+ * and re-laid-out emission rows live in a fixed scratch array in device
+ * memory, ctcalign_noalloc_scratch_bytes() = 64 MiB, one per device for the
+ * life of the process (its address is looked up when a context is created on
+ * the device).  Every call on one device shares that array: calls that
+ * overlap in time on one device race and must be ordered by the caller (one
+ * stream, or events).  Alignments run on one workgroup (S <= 32768): the
+ * backpointers take about T * S * 3/16 bytes (plus T * 32 or T * 256 floats
+ * when C is not 32 or 256, or the emission is not 16-byte aligned).
+ * Errors: EINVAL as ctcalign_align_ex; ENOMEM when the call needs more
+ * scratch than the array holds (nothing is launched); EDEVICE if the
+ * context's device has no scratch address. */
+int ctcalign_align_noalloc(ctcalign_ctx *ctx, const float *emission, int32_t T, int32_t C,
+                           const int32_t *labels, int32_t L, int32_t blank,
+                           int32_t *out_path, float *out_scores, float *out_total,
+                           int32_t *out_status, ctcalign_stream stream);
+
+/* Size in bytes of the per-device scratch array of ctcalign_align_noalloc. */
+size_t ctcalign_noalloc_scratch_bytes(void);
+
 /* Token spans of an alignment: the frame-level path (paper Sec. 4,
  * "CTC-based forced alignment") grouped into one segment per transcript
  * token, the step that turns a frame alignment into token time stamps for

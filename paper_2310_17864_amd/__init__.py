@@ -25,7 +25,7 @@ from . import _lib
 from ._lib import (CtcAlignError, EAGAIN, EBUSY, EDEVICE, EINFEASIBLE, EINVAL, ENOMEM, OK,
                    LibraryMissing, strerror)
 
-__all__ = ["align", "token_spans", "align_many_launches", "Context", "Plan", "Server", "workspace_bytes", "strerror",
+__all__ = ["align", "align_noalloc", "token_spans", "align_many_launches", "Context", "Plan", "Server", "workspace_bytes", "strerror",
            "CtcAlignError", "LibraryMissing", "OK", "EINVAL", "EINFEASIBLE", "ENOMEM",
            "EDEVICE", "EAGAIN", "EBUSY"]
 
@@ -173,6 +173,33 @@ def align(emission, labels, blank: int = 0, out=None, workspace=None, sync: bool
         st = int(status.item())
         if st != OK:
             raise CtcAlignError(st, "align")
+    return path, scores, total, status
+
+
+def align_noalloc(emission, labels, blank: int = 0, out=None):
+    """align() through ctcalign_align_noalloc: no device allocation inside
+    the library call (backpointers in the library's fixed per-device scratch
+    array; calls must not overlap on one device).  Returns (path, scores,
+    total, status) device tensors on the current stream, without waiting."""
+    torch = _torch()
+    _check_dev_tensor(emission, torch.float32, "emission")
+    _check_dev_tensor(labels, torch.int32, "labels")
+    if emission.dim() != 2:
+        raise ValueError("emission must be [T, C]")
+    T, C = emission.shape
+    L = labels.numel()
+    dev = emission.device
+    ctx = context(dev.index)
+    if out is None:
+        out = (torch.empty(T, dtype=torch.int32, device=dev),
+               torch.empty(T, dtype=torch.float32, device=dev),
+               torch.empty(1, dtype=torch.float32, device=dev),
+               torch.empty(1, dtype=torch.int32, device=dev))
+    path, scores, total, status = out
+    _lib.check(_lib.load().ctcalign_align_noalloc(
+        ctx.handle, emission.data_ptr(), T, C, labels.data_ptr() if L else None, L, blank,
+        path.data_ptr(), scores.data_ptr(), total.data_ptr(), status.data_ptr(),
+        _stream_handle(dev)), "align_noalloc")
     return path, scores, total, status
 
 

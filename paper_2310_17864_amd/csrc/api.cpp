@@ -66,16 +66,6 @@ int launch_multi_serial(int device, const Inst& in, hipStream_t st) {
   return CTCALIGN_OK;
 }
 
-int validate_one(const float* em, int32_t T, int32_t C, const int32_t* labels, int32_t L,
-                 int32_t blank, const void* path, const void* scores) {
-  if (!em || !path || !scores) return CTCALIGN_EINVAL;
-  if (T < 1 || T > (1 << 30) || C < 1 || C > kMaxC || L < 0) return CTCALIGN_EINVAL;
-  if (L > 0 && !labels) return CTCALIGN_EINVAL;
-  if (blank < 0 || blank >= C) return CTCALIGN_EINVAL;
-  if (2 * (int64_t)L + 1 > kMaxS) return CTCALIGN_EINVAL;
-  return CTCALIGN_OK;
-}
-
 // Fills geometry and LDS stride fields of an Inst for a single launch.
 void geometry_one(const ctcalign_ctx* ctx, Inst& in) {
   const int S = 2 * in.L + 1;
@@ -272,6 +262,9 @@ int ctcalign_ctx_create(int device, ctcalign_ctx** out) {
   }
   c->num_cu = prop.multiProcessorCount;
   c->tune.load_default(c->num_cu);
+  // the allocation-free entry point's scratch array: its address on this
+  // device, looked up once (the device is current here)
+  if (noalloc_setup(device) != CTCALIGN_OK) CTCA_LOG(1, "no scratch array on device %d", device);
   if (const char* tc = std::getenv("CTCALIGN_TUNE_CACHE")) {
     if (ctcalign_tune_load(c, tc) != CTCALIGN_OK) CTCA_LOG(1, "tuning cache %s not (fully) loaded", tc);
   }

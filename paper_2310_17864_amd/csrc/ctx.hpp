@@ -78,6 +78,23 @@ inline int row_stride_for(int C) { return C <= 32 ? 32 : 256; }
 
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// Host-checkable arguments of one alignment.
+inline int validate_one(const float* em, int32_t T, int32_t C, const int32_t* labels, int32_t L,
+                        int32_t blank, const void* path, const void* scores) {
+  if (!em || !path || !scores) return CTCALIGN_EINVAL;
+  if (T < 1 || T > (1 << 30) || C < 1 || C > kMaxC || L < 0) return CTCALIGN_EINVAL;
+  if (L > 0 && !labels) return CTCALIGN_EINVAL;
+  if (blank < 0 || blank >= C) return CTCALIGN_EINVAL;
+  if (2 * (int64_t)L + 1 > kMaxS) return CTCALIGN_EINVAL;
+  return CTCALIGN_OK;
+}
+
+// The allocation-free entry point's per-device scratch array (noalloc.hip):
+// noalloc_setup looks up its address on `device` (which must be current)
+// once; noalloc_scratch returns it (nullptr before setup or on failure).
+int noalloc_setup(int device);
+void* noalloc_scratch(int device);
+
 }  // namespace ctca
 
 struct ctcalign_ctx {
