@@ -152,6 +152,38 @@ int ctcalign_align_ex(ctcalign_ctx *ctx, const float *emission, int32_t T, int32
                       int32_t *out_status, void *workspace, size_t ws_bytes,
                       ctcalign_stream stream);
 
+/* Memory-bounded forced alignment of one long utterance: the same
+ * alignment (paper Sec. 4, "CTC-based forced alignment", whose GPU path the
+ * paper presents for long audio files), bitwise the same results as
+ * ctcalign_align_ex, with a workspace that grows like sqrt(T) instead of T.
+ * A first pass runs the recursion over all frames and keeps only the column
+ * a_t of every K-th frame (4 bytes per state); then each stretch of K frames,
+ * last first, is run again from its column with backpointers for those K
+ * frames only, and backtracked from the state where the stretch after it
+ * began.  Workspace: about (T/K) * S * 4 + K * S * 3/16 bytes
+ * (ctcalign_checkpointed_workspace_bytes); the forward recursion runs twice.
+ * K: frames per stretch, rounded up to a multiple of 32; 0 picks the
+ * larger of about 4.6 * sqrt(T), which minimises the workspace, and four
+ * times the pipeline fill of a stretch (32 frames per workgroup of eight
+ * wavefronts), which keeps the second pass within a small factor of the
+ * first.  Runs in the
+ * multi-workgroup layout (513 <= S <= 32768, T < 2^21 - 64); other shapes,
+ * and T <= K + 1, take the regular path of ctcalign_align_ex, whose
+ * workspace ctcalign_checkpointed_workspace_bytes then reports.  Launches
+ * are ordered on `stream` and serialised with other multi-workgroup launches
+ * as described for ctcalign_align_ex.  Errors as ctcalign_align_ex; EINVAL
+ * also for K < 0 or a workspace smaller than required. */
+int ctcalign_align_checkpointed(ctcalign_ctx *ctx, const float *emission, int32_t T, int32_t C,
+                                const int32_t *labels, int32_t L, int32_t blank,
+                                int32_t *out_path, float *out_scores, float *out_total,
+                                int32_t *out_status, int32_t K, void *workspace, size_t ws_bytes,
+                                ctcalign_stream stream);
+
+/* Workspace bytes of ctcalign_align_checkpointed for (T, L, C, K); 0 on an
+ * invalid shape. */
+size_t ctcalign_checkpointed_workspace_bytes(ctcalign_ctx *ctx, int32_t T, int32_t L, int32_t C,
+                                             int32_t K);
+
 /* For callers that cannot allocate device memory (work recorded under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * alignment of ctcalign_align_ex, bitwise the same results, asynchronous on

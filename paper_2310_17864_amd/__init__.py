@@ -25,7 +25,7 @@ from . import _lib
 from ._lib import (CtcAlignError, EAGAIN, EBUSY, EDEVICE, EINFEASIBLE, EINVAL, ENOMEM, OK,
                    LibraryMissing, strerror)
 
-__all__ = ["align", "align_noalloc", "token_spans", "align_many_launches", "Context", "Plan", "Server", "workspace_bytes", "strerror",
+__all__ = ["align", "align_checkpointed", "checkpointed_workspace_bytes", "align_noalloc", "token_spans", "align_many_launches", "Context", "Plan", "Server", "workspace_bytes", "strerror",
            "CtcAlignError", "LibraryMissing", "OK", "EINVAL", "EINFEASIBLE", "ENOMEM",
            "EDEVICE", "EAGAIN", "EBUSY"]
 
@@ -174,6 +174,46 @@ def align(emission, labels, blank: int = 0, out=None, workspace=None, sync: bool
         if st != OK:
             raise CtcAlignError(st, "align")
     return path, scores, total, status
+
+
+def align_checkpointed(emission, labels, blank: int = 0, every: int = 0, out=None,
+                       workspace=None, sync: bool = True):
+    """align() with a workspace that grows like sqrt(T): column checkpoints
+    every `every` frames (0: about 4.6 sqrt(T)) and backpointers for one
+    stretch at a time, bitwise the same results (ctcalign_align_checkpointed)."""
+    torch = _torch()
+    _check_dev_tensor(emission, torch.float32, "emission")
+    _check_dev_tensor(labels, torch.int32, "labels")
+    if emission.dim() != 2:
+        raise ValueError("emission must be [T, C]")
+    T, C = emission.shape
+    L = labels.numel()
+    dev = emission.device
+    ctx = context(dev.index)
+    if out is None:
+        out = (torch.empty(T, dtype=torch.int32, device=dev),
+               torch.empty(T, dtype=torch.float32, device=dev),
+               torch.empty(1, dtype=torch.float32, device=dev),
+               torch.empty(1, dtype=torch.int32, device=dev))
+    path, scores, total, status = out
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    _lib.check(_lib.load().ctcalign_align_checkpointed(
+        ctx.handle, emission.data_ptr(), T, C, labels.data_ptr() if L else None, L, blank,
+        path.data_ptr(), scores.data_ptr(), total.data_ptr(), status.data_ptr(), int(every),
+        ws_ptr, ws_bytes, _stream_handle(dev)), "align_checkpointed")
+    if sync:
+        st = int(status.item())
+        if st != OK:
+            raise CtcAlignError(st, "align_checkpointed")
+    return path, scores, total, status
+
+
+def checkpointed_workspace_bytes(T: int, L: int, C: int, every: int = 0,
+                                 device: Optional[int] = None) -> int:
+    return int(_lib.load().ctcalign_checkpointed_workspace_bytes(context(device).handle, T, L, C,
+                                                                 int(every)))
 
 
 def align_noalloc(emission, labels, blank: int = 0, out=None):

@@ -47,6 +47,9 @@ _PROTOS = {
     "ctcalign_workspace_bytes": (SZ, [P, I32, I32, I32]),
     "ctcalign_align": (ctypes.c_int, [P, I32, I32, P, I32, I32, P, P]),
     "ctcalign_align_ex": (ctypes.c_int, [P, P, I32, I32, P, I32, I32, P, P, P, P, P, SZ, P]),
+    "ctcalign_align_checkpointed": (ctypes.c_int, [P, P, I32, I32, P, I32, I32, P, P, P, P, I32,
+                                                   P, SZ, P]),
+    "ctcalign_checkpointed_workspace_bytes": (SZ, [P, I32, I32, I32, I32]),
     "ctcalign_align_noalloc": (ctypes.c_int, [P, P, I32, I32, P, I32, I32, P, P, P, P, P]),
     "ctcalign_noalloc_scratch_bytes": (SZ, []),
     "ctcalign_token_spans": (ctypes.c_int, [P, P, I32, I32, I32, P, P, P, P, P, P]),

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -41,7 +42,10 @@ struct MultiSync {
 };
 MultiSync g_msync[kMaxDevices];
 
-int launch_multi_serial(int device, const Inst& in, hipStream_t st) {
+// ck / mode: a pass of the checkpointed long form (launch_multi_ck) instead
+// of a whole alignment.
+int launch_multi_serial(int device, const Inst& in, hipStream_t st, const CkArgs* ck = nullptr,
+                        int mode = kModeFull) {
   if (device < 0 || device >= kMaxDevices) return CTCALIGN_EDEVICE;
   MultiSync& m = g_msync[device];
   std::lock_guard<std::mutex> lk(m.mu);
@@ -60,7 +64,10 @@ int launch_multi_serial(int device, const Inst& in, hipStream_t st) {
     m.gen = 0;
   }
   ++m.gen;
-  HIP_TRY(launch_multi(in, m.region, m.gen, st));
+  if (ck)
+    HIP_TRY(launch_multi_ck(in, m.region, m.gen, *ck, mode, st));
+  else
+    HIP_TRY(launch_multi(in, m.region, m.gen, st));
   HIP_TRY(hipEventRecord(m.last, st));
   m.used = true;
   return CTCALIGN_OK;
@@ -142,6 +149,54 @@ int launch_single(ctcalign_ctx* ctx, const float* emission, int32_t T, int32_t C
     ctx->arena_used = true;
   }
   return CTCALIGN_OK;
+}
+
+// ---- checkpointed long form ---------------------------------------------------
+
+// Layout of a checkpointed alignment: the multi-workgroup layout with the
+// fewest states per lane that holds S (W = 0 if none does: the regular path
+// runs), K frames per stretch and the workspace parts.
+struct CkPlan {
+  Geo g{0, 0};
+  int K = 0;
+  int nstretch = 0;       // stretches of K frames (the last may be shorter)
+  int64_t spad = 0;       // floats per column
+  size_t off_cols = 0, off_bp = 0, bytes = 0;   // [state | columns | backpointers]
+};
+
+CkPlan ck_plan(int32_t T, int32_t L, int32_t K) {
+  CkPlan p;
+  const int S = 2 * L + 1;
+  if (T > kXMaxT) return p;
+  for (int M : kMenuMulti) {
+    const int W = (S + kWave * M - 1) / (kWave * M);
+    if (geometry_supported_ck(W, M) && geo_ok(S, W, M)) {
+      p.g = Geo{W, M};
+      break;
+    }
+  }
+  if (p.g.W == 0) return p;
+  if (K <= 0) {
+    // about sqrt(T * 4 / (3/16)) minimises columns (4 bytes per state) plus
+    // one stretch's backpointers (3/16 byte per state and frame); but each
+    // stretch first fills the workgroup pipeline (a workgroup starts about
+    // one 32-frame block after the one below it), so a stretch spans at
+    // least four fills
+    const int groups = (p.g.W + kXWaves - 1) / kXWaves;
+    K = std::max((int)(4.6 * std::sqrt((double)T)), 4 * kBlk * groups);
+  }
+  K = std::max(kBlk, (K + kBlk - 1) / kBlk * kBlk);
+  if ((int64_t)T <= (int64_t)K + 1) {   // one stretch: the regular path
+    p.g = Geo{0, 0};
+    return p;
+  }
+  p.K = K;
+  p.nstretch = (T - 1 + K - 1) / K;
+  p.spad = (int64_t)p.g.W * kWave * p.g.M;
+  p.off_cols = 256;
+  p.off_bp = p.off_cols + round_up((size_t)p.nstretch * (size_t)p.spad * sizeof(float), 256);
+  p.bytes = p.off_bp + round_up((size_t)bp_words(K + 1, p.g.W, p.g.M) * 4, 256);
+  return p;
 }
 
 uint64_t fnv(uint64_t h, const void* p, size_t n) {
@@ -335,6 +390,99 @@ int ctcalign_align(const float* emission, int32_t T, int32_t C, const int32_t* l
                          ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return ctx->h_status[0];
+}
+
+size_t ctcalign_checkpointed_workspace_bytes(ctcalign_ctx* ctx, int32_t T, int32_t L, int32_t C,
+                                             int32_t K) {
+  if (!ctx || T < 1 || L < 0 || C < 1 || C > kMaxC || 2 * (int64_t)L + 1 > kMaxS || K < 0) return 0;
+  const CkPlan p = ck_plan(T, L, K);
+  if (p.g.W == 0) return ctcalign_workspace_bytes(ctx, T, L, C);
+  return p.bytes;
+}
+
+int ctcalign_align_checkpointed(ctcalign_ctx* ctx, const float* emission, int32_t T, int32_t C,
+                                const int32_t* labels, int32_t L, int32_t blank, int32_t* out_path,
+                                float* out_scores, float* out_total, int32_t* out_status, int32_t K,
+                                void* workspace, size_t ws_bytes, ctcalign_stream stream) {
+  if (!ctx || K < 0) return CTCALIGN_EINVAL;
+  int rc = validate_one(emission, T, C, labels, L, blank, out_path, out_scores);
+  if (rc) return rc;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const CkPlan p = ck_plan(T, L, K);
+  if (p.g.W == 0)   // no checkpointed layout, or a single stretch
+    return launch_single(ctx, emission, T, C, labels, L, blank, out_path, out_scores, out_total,
+                         out_status, workspace, ws_bytes, st);
+  if (workspace && (ws_bytes < p.bytes || (reinterpret_cast<uintptr_t>(workspace) & 255u)))
+    return CTCALIGN_EINVAL;
+  const int stride = row_stride_for(C);
+  const bool padded = !(C == stride && aligned16(emission));
+  const bool shared = !workspace || padded;
+  if (shared) {
+    if (!ctx->arena_ev) HIP_TRY(hipEventCreateWithFlags(&ctx->arena_ev, hipEventDisableTiming));
+    if (ctx->arena_used && ctx->arena_stream != st) HIP_TRY(hipStreamWaitEvent(st, ctx->arena_ev, 0));
+  }
+  char* ws;
+  if (workspace) {
+    ws = static_cast<char*>(workspace);
+  } else {
+    rc = ctx->ws.reserve(p.bytes);
+    if (rc) return rc;
+    ws = static_cast<char*>(ctx->ws.ptr);
+  }
+  const float* em = emission;
+  if (padded) {
+    rc = ctx->pad.reserve((size_t)T * stride * sizeof(float));
+    if (rc) return rc;
+    const PadDesc pd{emission, static_cast<float*>(ctx->pad.ptr), T, C, stride, 0};
+    HIP_TRY(launch_pad_one(pd, st));
+    em = static_cast<float*>(ctx->pad.ptr);
+  }
+  CkArgs ck{};
+  ck.ck = reinterpret_cast<float*>(ws + p.off_cols);
+  ck.state = reinterpret_cast<int32_t*>(ws);
+  ck.spad = (int32_t)p.spad;
+  ck.every = p.K;
+  Inst in{};
+  in.C = C;
+  in.L = L;
+  in.blank = blank;
+  in.lab = labels;
+  in.stride = stride;
+  in.W = p.g.W;
+  in.M = p.g.M;
+  in.prio = 0;
+  // first pass: the whole alignment, columns only
+  in.T = T;
+  in.em = em;
+  in.path = out_path;
+  in.scores = out_scores;
+  in.total = out_total;
+  in.status = out_status;
+  in.bp = reinterpret_cast<uint32_t*>(ws + p.off_bp);   // not written in this pass
+  CTCA_LOG(2, "align_checkpointed T=%d C=%d L=%d -> W=%d M=%d K=%d stretches=%d bytes=%zu", T, C, L,
+           in.W, in.M, p.K, p.nstretch, p.bytes);
+  rc = launch_multi_serial(ctx->device, in, st, &ck, kModeCkFirst);
+  if (rc) return rc;
+  // stretches, last first: stretch k covers frames kK .. min(kK + K, T - 1)
+  in.total = nullptr;
+  for (int k = p.nstretch - 1; k >= 0; --k) {
+    const int t0 = k * p.K;
+    const int Tk = std::min(p.K, T - 1 - t0) + 1;
+    in.T = Tk;
+    in.em = em + (int64_t)t0 * stride;
+    in.path = out_path + t0;
+    in.scores = out_scores + t0;
+    ck.col = k;
+    rc = launch_multi_serial(ctx->device, in, st, &ck, kModeCkSeg);
+    if (rc) return rc;
+  }
+  if (shared) {
+    HIP_TRY(hipEventRecord(ctx->arena_ev, st));
+    ctx->arena_stream = st;
+    ctx->arena_used = true;
+  }
+  return CTCALIGN_OK;
 }
 
 int ctcalign_token_spans(const int32_t* path, const float* scores, int32_t T, int32_t blank,

@@ -282,10 +282,15 @@ struct FwdOut {
 // cleared it and passed a workgroup barrier after `prologue_check`.
 // kX: multi layout; `sy` is then this workgroup's SegSync array and xl says
 // which neighbours sit in other workgroups.
-template <int M, bool kX = false>
+//
+// kMode (checkpointed long form, CkArgs): kModeCkFirst keeps the column of
+// every ck->every-th frame and stores no backpointers; kModeCkSeg starts from
+// column ck->col instead of frame 0 and has no end state of its own.
+template <int M, bool kX = false, int kMode = kModeFull>
 __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, const int lane,
                                                   const Ring& ring, SegSync* sy, bool labels_bad,
-                                                  const XLink& xl = XLink{}) {
+                                                  const XLink& xl = XLink{},
+                                                  const CkArgs* ck = nullptr) {
   const int T = in.T, L = in.L, blank = in.blank, W = in.W;
   const int S = 2 * L + 1;                  // state counts fit int32 (host-checked)
   const int sbase = (w * kWave + lane) * M;
@@ -311,14 +316,26 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
     skip[jj] = sk ? 0.0f : neg_inf();
   }
 
-  // a3: frame 0.  Only states 0 and 1 start finite.
+  // a3: frame 0.  Only states 0 and 1 start finite.  (A checkpointed
+  // stretch starts from its stored column instead.)
   float a[M];
+  if constexpr (kMode == kModeCkSeg) {
+    const float* col = ck->ck + (int64_t)ck->col * ck->spad + sbase;
 #pragma unroll
-  for (int j = 0; j < M; ++j) {
-    const int s = sbase + j;
-    a[j] = neg_inf();
-    if (s == 0) a[j] = em[blank];
-    if (s == 1 && S > 1) a[j] = em[in.lab[0]];
+    for (int j = 0; j < M; ++j) a[j] = col[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int s = sbase + j;
+      a[j] = neg_inf();
+      if (s == 0) a[j] = em[blank];
+      if (s == 1 && S > 1) a[j] = em[in.lab[0]];
+    }
+  }
+  if constexpr (kMode == kModeCkFirst) {
+    float* col = ck->ck + sbase;   // column 0
+#pragma unroll
+    for (int j = 0; j < M; ++j) col[j] = a[j];
   }
 
   const bool has_next = w + 1 < W, has_prev = w > 0;
@@ -489,13 +506,15 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
       }
       // a5: flush the group's backpointer words; frame i of plane r of word q
       // lands at bit 31 - (R*i + r) (left-aligned when the group is short)
-      const int gi = 4 * b + g;
-      uint32_t* dst = bpw + (int64_t)gi * NQ * kWave;
-      const int nf = ng < kUnroll ? ng : kUnroll;
+      if constexpr (kMode != kModeCkFirst) {
+        const int gi = 4 * b + g;
+        uint32_t* dst = bpw + (int64_t)gi * NQ * kWave;
+        const int nf = ng < kUnroll ? ng : kUnroll;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int sh = 32 - planes_in_word(M, q) * nf;
-        dst[q * kWave] = acc[q] << sh;
+        for (int q = 0; q < NQ; ++q) {
+          const int sh = 32 - planes_in_word(M, q) * nf;
+          dst[q * kWave] = acc[q] << sh;
+        }
       }
       if constexpr (kGroupFlow) {
         if (has_next && !next_x) lds_store_rel(&me->prod, ubase + ne + 1);
@@ -503,6 +522,16 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
       }
     }
 
+    if constexpr (kMode == kModeCkFirst) {
+      // the column of frame 32b+32 when it starts a later stretch (every
+      // stretch start below T-1 ends a whole block)
+      const int tl = 32 * b + n;
+      if (n == kBlk && tl % ck->every == 0 && tl < T - 1) {
+        float* col = ck->ck + (int64_t)(tl / ck->every) * ck->spad + sbase;
+#pragma unroll
+        for (int j = 0; j < M; ++j) col[j] = a[j];
+      }
+    }
     if (next_x && alive) x_push(xl.out_ch, me, 32 * b + 1, n, lane, xl.tag);   // values 32b+1 .. 32b+n
     if constexpr (!kGroupFlow) {
       if (has_next && !next_x) lds_store_rel(&me->prod, 32 * b + n + 1);
@@ -513,7 +542,7 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   wait_dma();   // no copy into LDS may outlive this instance
 
   // a6: end state, in the segment that holds S-1 and S-2
-  if (w == W - 1) {
+  if (w == W - 1 && kMode != kModeCkSeg) {
     float v1 = neg_inf(), v2 = neg_inf();
 #pragma unroll
     for (int j = 0; j < M; ++j) {
@@ -743,8 +772,11 @@ __device__ __forceinline__ void fill_outputs(const Inst& in, int lane, int path_
   }
 }
 
+// out_state (nullable): receives the state of frame 0 (the checkpointed
+// long form starts the previous stretch's backtrack there).
 template <int M>
-__device__ __forceinline__ void backtrack(const Inst& in, const FwdOut& fo, int status_in, int lane) {
+__device__ __forceinline__ void backtrack(const Inst& in, const FwdOut& fo, int status_in, int lane,
+                                          int32_t* out_state = nullptr) {
   const int T = in.T, RS = in.stride, blank = in.blank;   // RS: emission row stride
   const float* em = in.em;
   int status = status_in;
@@ -843,6 +875,7 @@ __device__ __forceinline__ void backtrack(const Inst& in, const FwdOut& fo, int 
     if (lane == 0) {
       const int lab0 = (e % 2 == 0) ? blank : in.lab[(e - 1) / 2];
       store_untracked(in.path, (uint32_t)lab0);
+      if (out_state) store_untracked(out_state, (uint32_t)e);
     }
     // per-frame scores: emission[t, path[t]], four independent gathers per
     // lane in flight (the path stores above are complete after the wait)

@@ -65,6 +65,25 @@ struct XSync {
 };
 __host__ __device__ constexpr bool geometry_is_multi(int W, int M) { return M <= 16 && W > 4; }
 
+// Checkpointed long form (memory-bounded): a first pass over the whole
+// alignment keeps only the column a_t of every K-th frame (t = 0, K, 2K, ...)
+// and no backpointers; then, from the last K-frame stretch to the first, each
+// stretch is run again from its column with backpointers for its K frames
+// only, and backtracked from the state the stretch after it ended on.  The
+// same arithmetic in the same order gives the same columns, so the path is
+// bitwise the one of the full run.  Columns hold every state slot of the
+// layout (W*64*M floats, padding slots included) in state order.
+enum : int32_t { kModeFull = 0, kModeCkFirst = 1, kModeCkSeg = 2 };
+struct CkArgs {
+  float* ck;         // column k (a_{kK}) at ck + k * spad
+  int32_t* state;    // [0] state to start the next stretch's backtrack from,
+                     // [1] status of the first pass (stretches run only if 0)
+  int32_t spad;      // floats per column
+  int32_t every;     // K: frames per stretch, a multiple of kBlk
+  int32_t col;       // kModeCkSeg: the column this launch starts from
+  int32_t pad_;
+};
+
 // A workgroup-sized work item of the persistent kernel: wave k runs segment
 // seg[k] of instance inst[k] (inst < 0: idle); the W segments of an instance
 // sit on consecutive waves starting at first[k].

@@ -25,6 +25,11 @@ bool geometry_supported_long_batch(int W, int M);
 // the batch's longest chains: one alignment per 8-wave workgroup, M in {4..12}
 bool geometry_supported_crit(int W, int M);
 hipError_t launch_persistent_crit(const Inst* d_insts, const int* d_order, int n, hipStream_t st);
+// the checkpointed long form: one pass (mode kModeCkFirst or kModeCkSeg) of
+// an alignment in the multi-workgroup layout, as launch_multi
+bool geometry_supported_ck(int W, int M);
+hipError_t launch_multi_ck(const Inst& in, XSync* xs, uint32_t gen, const CkArgs& ck, int mode,
+                           hipStream_t st);
 hipError_t launch_spans(const int32_t* path, const float* scores, int T, int blank, int max_spans,
                         int32_t* tok, int32_t* start, int32_t* end, float* score, int32_t* count,
                         hipStream_t st);

@@ -88,11 +88,34 @@ __device__ __forceinline__ bool wait_eq_sys(const int* p, int want) {
   return false;
 }
 
+// First pass of the checkpointed long form, top segment: the outcome (as
+// the backtrack would report it; on failure the outputs are filled here and
+// no stretch runs) and the end state the last stretch starts from.
+__device__ __forceinline__ void ck_first_finish(const Inst& in, const FwdOut& fo, int status_in,
+                                                int lane, const CkArgs* ck) {
+  int status = status_in;
+  float total = fo.total;
+  if (status == kOk && !fo.ok) status = kEdevice;
+  if (status == kOk && total == neg_inf()) status = kEinfeasible;
+  if (status != kOk) {
+    fill_outputs(in, lane, -1, status == kEinfeasible ? neg_inf() : __builtin_nanf(""));
+    if (status != kEinfeasible) total = __builtin_nanf("");
+  }
+  if (lane == 0) {
+    if (in.total) *in.total = total;
+    if (in.status) *in.status = status;
+    ck->state[0] = fo.send;
+    ck->state[1] = status;
+  }
+}
+
 // Segment w = g * kWG + wl of a multi-workgroup alignment on wave wl of
 // workgroup g (kWG waves per workgroup; sy[kWG] holds the incoming copy).
-template <int M, int kWG>
+// kMode / ck: the passes of the checkpointed long form (CkArgs).
+template <int M, int kWG, int kMode = kModeFull>
 __device__ __forceinline__ void run_multi(const Inst& in, XSync* xs, uint32_t tag, SegSync* sy,
-                                          const Ring& ring, int g, int wl, int lane, bool bad) {
+                                          const Ring& ring, int g, int wl, int lane, bool bad,
+                                          const CkArgs* ck = nullptr) {
   const int w = g * kWG + wl;
   if (w >= in.W) return;
   XLink xl;
@@ -101,7 +124,7 @@ __device__ __forceinline__ void run_multi(const Inst& in, XSync* xs, uint32_t ta
   xl.in_lds = sy + kWG;
   if (wl == 0 && g > 0) xl.in_ch = &xs->ch[g - 1];
   if (wl == kWG - 1 && w + 1 < in.W) xl.out_ch = &xs->ch[g];
-  const FwdOut fo = segment_forward<M, true>(in, w, lane, ring, sy, bad, xl);
+  const FwdOut fo = segment_forward<M, true, kMode>(in, w, lane, ring, sy, bad, xl, ck);
   if (w + 1 < in.W) {
     // backpointers visible device-wide, then the flag
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -113,7 +136,18 @@ __device__ __forceinline__ void run_multi(const Inst& in, XSync* xs, uint32_t ta
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     FwdOut f2 = fo;
     f2.ok = ok ? 1 : 0;
-    backtrack<M>(in, f2, bad ? kEinval : kOk, lane);
+    if constexpr (kMode == kModeCkFirst) {
+      ck_first_finish(in, f2, bad ? kEinval : kOk, lane, ck);
+    } else if constexpr (kMode == kModeCkSeg) {
+      // a stretch: the first pass settled the outcome (only an expired wait
+      // can still fail it); start where the stretch after this one ended
+      f2.total = 0.0f;
+      f2.send = __builtin_amdgcn_readfirstlane(ck->state[0]);
+      backtrack<M>(in, f2, kOk, lane, ck->state);
+      if (!ok && lane == 0) ck->state[1] = kEdevice;
+    } else {
+      backtrack<M>(in, f2, bad ? kEinval : kOk, lane);
+    }
   }
 }
 
@@ -155,5 +189,6 @@ constexpr int kPackMenuK[] = {2, 4, 6, 8, 10, 12, 14, 16};       // k_persistent
 constexpr int kMultiMenu[] = {2, 4, 6, 8, 10, 12, 14, 16};       // k_multi
 constexpr int kCritMenu[] = {4, 6, 8, 10, 12};                   // k_persistent_crit
 constexpr int kServePartMenu[] = {4, 6, 8};                      // k_serve, multi-workgroup parts
+constexpr int kCkMenu[] = {2, 4, 6, 8, 10, 12, 14, 16};          // k_multi_ck
 
 }  // namespace ctca
