@@ -1,12 +1,16 @@
-"""CPU oracle for CTC forced alignment -- test infrastructure only.
+"""CPU oracles for CTC forced alignment and CTC prefix beam search -- test
+infrastructure only.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The library under
 ``paper_2310_17864_amd`` never does, and shares no code with it.
 
-The arithmetic lives in ``viterbi.c`` (plain C, one float add per state and
-frame, strict-greater tie rule); this module only marshals numpy arrays into
-it.  Status codes: 0 ok, 1 invalid labels, 2 infeasible.
+The arithmetic lives in ``viterbi.c`` (forced alignment: plain C, one float
+add per state and frame, strict-greater tie rule) and ``beam.c`` (prefix
+beam search with blank collapse, float32 probabilities, fixed operation
+order and tie rule); this module only marshals numpy arrays into them.
+Status codes: 0 ok, 1 invalid input, 2 infeasible (alignment) / no
+hypothesis (beam search).
 """
 from __future__ import annotations
 
@@ -18,7 +22,7 @@ from typing import Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "viterbi.c")
+_SRCS = [os.path.join(_HERE, "viterbi.c"), os.path.join(_HERE, "beam.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, EINVAL, EINFEASIBLE, ENOMEM = 0, 1, 2, 3
@@ -27,12 +31,14 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile viterbi.c with gcc: -O2, no fast-math, no FMA contraction."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile the C sources with gcc: -O2, no fast-math, no FMA contraction."""
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f)
+                                            for f in _SRCS)
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared",
                                "-ffp-contract=off", "-fno-fast-math", "-Wall",
-                               "-o", tmp, _SRC, "-lpthread", "-lm"])
+                               "-o", tmp] + _SRCS + ["-lpthread", "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -51,6 +57,16 @@ def _load():
         lib.oracle_align_batch_f32.argtypes = [i32, P, P, P, P, P, P, P, i32,
                                                P, P, P, P, P, i32]
         lib.oracle_align_batch_f32.restype = ctypes.c_int
+        f32 = ctypes.c_float
+        lib.oracle_blank_collapse.argtypes = [P, i32, i32, i32, f32, P]
+        lib.oracle_blank_collapse.restype = ctypes.c_int
+        lib.oracle_beam_decode.argtypes = [P, i32, i32, i32, i32, f32, P, P, P, P, P]
+        lib.oracle_beam_decode.restype = ctypes.c_int
+        lib.oracle_beam_decode_ex.argtypes = [P, i32, i32, i32, i32, f32, P, P, P, P, P, P, P]
+        lib.oracle_beam_decode_ex.restype = ctypes.c_int
+        lib.oracle_beam_decode_batch.argtypes = [i32, P, P, P, i32, i32, i32, f32, P, P, P, P,
+                                                 P, P, P, P, P, i32]
+        lib.oracle_beam_decode_batch.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -142,3 +158,82 @@ def token_spans(path, scores, blank: int = 0):
         sc.append(acc)
     return (np.array(tok, np.int32), np.array(st, np.int32), np.array(en, np.int32),
             np.array(sc, np.float32))
+
+
+# ---- CTC prefix beam search with blank collapse (beam.c) -------------------
+
+
+def blank_collapse(y: np.ndarray, blank: int = 0, a: float = 1.0) -> np.ndarray:
+    """Indices of the frames kept after blank collapse with threshold a
+    (frame t is a blank frame when y[t, blank] > a; every maximal run of blank
+    frames keeps its first frame only)."""
+    lib = _load()
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    T, V = y.shape
+    kept = np.empty(max(T, 1), np.int32)
+    n = lib.oracle_blank_collapse(_ptr(y), T, V, blank, np.float32(a), _ptr(kept))
+    return kept[:n].copy()
+
+
+def beam_decode(y: np.ndarray, blank: int = 0, beam: int = 10, a: float = 1.0, raw: bool = False):
+    """CTC prefix beam search over per-frame probabilities y [T, V] (float32)
+    after blank collapse with threshold a.  Returns (status, hyps, logp,
+    n_kept): the final beam in rank order as a list of int32 label arrays and
+    a float64 array of their log-probabilities; with raw=True also the scaled
+    totals (float32, relative to 2^E) and E."""
+    lib = _load()
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    T, V = y.shape
+    tok = np.zeros((beam, max(T, 1)), np.int32)
+    ln = np.zeros(beam, np.int32)
+    lp = np.zeros(beam, np.float64)
+    n_out = np.zeros(1, np.int32)
+    n_kept = np.zeros(1, np.int32)
+    sc = np.zeros(beam, np.float32)
+    ex = np.zeros(1, np.int32)
+    st = lib.oracle_beam_decode_ex(_ptr(y), T, V, blank, beam, np.float32(a), _ptr(tok), _ptr(ln),
+                                   _ptr(lp), _ptr(sc), _ptr(ex), _ptr(n_out), _ptr(n_kept))
+    n = int(n_out[0])
+    if raw:
+        return (st, [tok[k, :ln[k]].copy() for k in range(n)], lp[:n].copy(), int(n_kept[0]),
+                sc[:n].copy(), int(ex[0]))
+    return st, [tok[k, :ln[k]].copy() for k in range(n)], lp[:n].copy(), int(n_kept[0])
+
+
+def beam_decode_batch(packed: dict, blank: int = 0, beam: int = 10, a: float = 1.0,
+                      threads: int = 1, raw: bool = False):
+    """beam_decode over a packed batch (keys y, y_off, T, V).  Returns
+    (status[n], hyps: list of lists of label arrays, logp: list of float64
+    arrays, n_kept[n], threads_used)."""
+    lib = _load()
+    Ts = np.ascontiguousarray(packed["T"], dtype=np.int32)
+    n = int(Ts.shape[0])
+    V = int(packed["V"])
+    tok_off = np.zeros(n, np.int64)
+    if n:
+        tok_off[1:] = np.cumsum(Ts.astype(np.int64) * beam)[:-1]
+    tok = np.zeros(max(int(np.sum(Ts.astype(np.int64))) * beam, 1), np.int32)
+    ln = np.zeros(max(n * beam, 1), np.int32)
+    lp = np.zeros(max(n * beam, 1), np.float64)
+    n_out = np.zeros(max(n, 1), np.int32)
+    n_kept = np.zeros(max(n, 1), np.int32)
+    status = np.zeros(max(n, 1), np.int32)
+    sc = np.zeros(max(n * beam, 1), np.float32)
+    ex = np.zeros(max(n, 1), np.int32)
+    y = np.ascontiguousarray(packed["y"], dtype=np.float32)
+    y_off = np.ascontiguousarray(packed["y_off"], dtype=np.int64)
+    used = lib.oracle_beam_decode_batch(n, _ptr(y), _ptr(y_off), _ptr(Ts), V, blank, beam,
+                                        np.float32(a), _ptr(tok), _ptr(tok_off), _ptr(ln), _ptr(lp),
+                                        _ptr(sc), _ptr(ex), _ptr(n_out), _ptr(n_kept), _ptr(status),
+                                        int(threads))
+    hyps, logps, scaled = [], [], []
+    for i in range(n):
+        base = int(tok_off[i])
+        T = int(Ts[i])
+        hyps.append([tok[base + k * T: base + k * T + ln[i * beam + k]].copy()
+                     for k in range(int(n_out[i]))])
+        logps.append(lp[i * beam: i * beam + int(n_out[i])].copy())
+        scaled.append(sc[i * beam: i * beam + int(n_out[i])].copy())
+    if raw:
+        return status[:n].copy(), hyps, logps, n_kept[:n].copy(), used, scaled, ex[:n].copy()
+    return status[:n].copy(), hyps, logps, n_kept[:n].copy(), used

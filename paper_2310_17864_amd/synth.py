@@ -45,6 +45,7 @@ __all__ = [
     "Utterance", "Workload", "draw_labels", "planted_states", "emissions_around",
     "utterance", "cfg_single", "cfg_plain_batch", "cfg_long", "cfg_batched",
     "cfg_serving", "poisson_arrivals", "pack", "packed_parallel",
+    "decode_states", "decode_probs", "decode_packed",
 ]
 
 
@@ -332,3 +333,105 @@ def pack(utts: List[Utterance]):
     L = np.array([u.L for u in utts], dtype=np.int32)
     return dict(em=em, lab=lab, em_off=em_off, lab_off=lab_off, fr_off=fr_off,
                 T=T, C=C, L=L, frames=f)
+
+
+# ---- CTC beam search decoding workload ---------------------------------------
+#
+# Stand-in for the paper's decoder benchmark (Sec. 5, "CUDA CTC decoder":
+# LibriSpeech test-other through an acoustic model with a 500-token
+# vocabulary, beam 10; neither the dataset nor the model is used here).
+# Per-frame probabilities (softmax outputs, not logs) over V = 500 classes,
+# peaky like a trained CTC model's: a planted CTC path gives each label one
+# frame plus a geometric number of extra frames (mean 0.3), a blank between
+# equal labels at least one frame, and spreads the remaining frames
+# uniformly over the blank states, so most frames are blank; logits are
+# N(0, 1) plus a boost on the planted class, drawn per frame from U(10, 16)
+# (a confident frame: its class above ~0.96) with probability 0.9, else from
+# U(2, 8) (an uncertain frame); softmax in float64, rounded once to float32.
+# Labels are i.i.d. over the non-blank classes.  Utterances: T log-uniform in
+# [50, 900] frames, L ~ U{ceil(T/8)..floor(T/4)} tokens.
+
+
+def decode_states(rng: np.random.Generator, T: int, labels: np.ndarray) -> np.ndarray:
+    """State index (0..2L) of a planted CTC path with short label runs."""
+    L = int(labels.shape[0])
+    S = 2 * L + 1
+    dur = np.zeros(S, dtype=np.int64)
+    dur[1::2] = 1 + rng.geometric(1.0 / 1.3, size=L) - 1
+    if L > 1:
+        dur[2:2 * L:2] = (labels[1:] == labels[:-1]).astype(np.int64)
+    extra = T - int(dur.sum())
+    if extra < 0:   # label runs too long for T: fall back to single frames
+        dur[1::2] = 1
+        extra = T - int(dur.sum())
+    if extra < 0:
+        raise ValueError(f"T={T} too short for L={L}")
+    dur[0::2] += rng.multinomial(extra, np.full(L + 1, 1.0 / (L + 1)))
+    return np.repeat(np.arange(S, dtype=np.int32), dur)
+
+
+def decode_probs(rng: np.random.Generator, T: int, V: int, L: int, blank: int = 0,
+                 confident: float = 0.9, sigma: float = 1.0):
+    """(float32 probabilities [T, V], int32 planted labels [L])."""
+    labels = draw_labels(rng, L, V, blank, None)
+    states = decode_states(rng, T, labels)
+    logits = rng.standard_normal((T, V)) * sigma
+    cls = np.where(states % 2 == 0, blank,
+                   labels[np.maximum(states - 1, 0) // 2] if labels.size else blank)
+    sure = rng.random(T) < confident
+    boost = np.where(sure, rng.uniform(10.0, 16.0, size=T), rng.uniform(2.0, 8.0, size=T))
+    logits[np.arange(T), cls] += boost
+    z = logits - logits.max(axis=1, keepdims=True)
+    e = np.exp(z)
+    return (e / e.sum(axis=1, keepdims=True)).astype(np.float32), labels
+
+
+def _spec_decode(r: np.random.Generator, t_lo: int, t_hi: int):
+    T = _log_uniform_T(r, t_lo, t_hi)
+    L = int(r.integers(math.ceil(T / 8), T // 4 + 1))
+    return T, L
+
+
+_DEC = {}
+
+
+def _dec_work(i: int):
+    g = _DEC
+    r = np.random.default_rng(g["seqs"][i])
+    T, L = _spec_decode(r, g["t_lo"], g["t_hi"])
+    y, _ = decode_probs(r, T, g["V"], L, 0)
+    off = g["y_off"][i]
+    g["y"][off:off + T * g["V"]] = y.reshape(-1)
+    return i
+
+
+def decode_packed(n: int = 2048, t_lo: int = 50, t_hi: int = 900, V: int = 500, seed: int = 6,
+                  workers: int = 8):
+    """The decoding workload packed flat: dict(y, y_off, T, V, frames), rows of
+    utterance i at y[y_off[i]:...] ([T_i][V], offsets multiples of 64),
+    generated by `workers` forked processes into one shared mapping (call
+    before any GPU work).  Utterance i draws from SeedSequence(seed) child i."""
+    import mmap
+    import multiprocessing as mp
+    seqs = np.random.SeedSequence(seed).spawn(n + 1)
+    T = np.zeros(n, np.int32)
+    for i in range(n):
+        T[i], _ = _spec_decode(np.random.default_rng(seqs[i]), t_lo, t_hi)
+    y_off = np.zeros(n, np.int64)
+    e = 0
+    for i in range(n):
+        y_off[i] = e
+        e += (int(T[i]) * V + 63) // 64 * 64
+    buf = mmap.mmap(-1, max(e, 1) * 4)
+    y = np.frombuffer(buf, dtype=np.float32)
+    _DEC.clear()
+    _DEC.update(seqs=seqs, t_lo=t_lo, t_hi=t_hi, V=V, y_off=y_off, y=y)
+    if workers <= 1:
+        for i in range(n):
+            _dec_work(i)
+    else:
+        with mp.get_context("fork").Pool(workers) as pool:
+            for _ in pool.imap_unordered(_dec_work, range(n), chunksize=8):
+                pass
+    _DEC.clear()
+    return dict(y=y, y_off=y_off, T=T, V=V, frames=int(T.astype(np.int64).sum()), _buf=buf)
