@@ -282,6 +282,53 @@ int ctcalign_align_batched(ctcalign_ctx *ctx, int32_t N,
                            float *out_totals, int32_t *out_status,
                            ctcalign_stream stream);
 
+/* ---- CTC prefix beam search with blank collapse ---------------------------
+ * The paper's other GPU CTC kernel (Sec. 4, paragraph "CTC decoder"; Sec. 5,
+ * "CUDA CTC decoder", Table 3): lexicon-free CTC prefix beam search without
+ * a language model, every vocabulary class considered at every step, over
+ * per-frame PROBABILITIES (softmax outputs, float32, in [0, 1]), after
+ * blank collapse: a frame whose blank probability exceeds `threshold` is
+ * dropped when the frame before it is such a frame too (so every run of
+ * confident blank frames keeps its first frame; threshold >= 1 keeps every
+ * frame).  Per kept frame, each hypothesis (a label prefix with p_b, p_nb)
+ * stays (p_b' = (p_b + p_nb) * y[blank], p_nb' = p_nb * y[last]) or is
+ * extended by each class c != blank (p_nb += (c == last ? p_b : p_b + p_nb)
+ * * y[c], merged into an equal prefix already in the beam); the `beam`
+ * candidates of largest total form the next beam (ties: stays and
+ * extensions of better-ranked hypotheses first, then smaller classes).
+ * Scores are kept relative to a running power of two, so long inputs never
+ * underflow; every ranking decision and label is bitwise that of a plain
+ * float32 evaluation in the same order (no fused multiply-add).
+ *
+ * N utterances; utterance i has T[i] frames of V classes at probs +
+ * prob_off[i] (host arrays prob_off, T, tok_off).  Outputs (device):
+ *   out_tokens + tok_off[i]   `beam` rows of T[i] labels: row k holds
+ *                             hypothesis k's labels (out_len[i*beam + k] of them)
+ *   out_len[i*beam + k]       label count (0 for k >= out_nhyp[i])
+ *   out_logp[i*beam + k]      log-probability (nullable; -inf beyond out_nhyp)
+ *   out_scaled / out_exp[i]   the total probability as scaled * 2^exp
+ *                             (nullable; exact, for checking)
+ *   out_nhyp[i]               hypotheses in the final beam (<= beam), in rank
+ *                             order: row 0 is the decoded transcript
+ *   out_nkept[i]              frames kept by blank collapse (nullable)
+ *   out_status[i]             0, or 2 when no prefix keeps a positive
+ *                             probability (out_nhyp = 0)
+ * Limits: 2 <= V <= 1024, 1 <= beam <= 16.  One workgroup per utterance, all
+ * utterances in one launch on `stream`.  workspace (device, 256-byte
+ * aligned, >= ctcalign_beam_workspace_bytes) may be NULL: the context's
+ * arena is used, ordered across streams as for ctcalign_align_ex.
+ * Errors: EINVAL (arguments), ENOMEM, EDEVICE. */
+int ctcalign_beam_decode(ctcalign_ctx *ctx, int32_t N, const float *probs, const int64_t *prob_off,
+                         const int32_t *T, int32_t V, int32_t blank, int32_t beam, float threshold,
+                         int32_t *out_tokens, const int64_t *tok_off, int32_t *out_len,
+                         float *out_logp, float *out_scaled, int32_t *out_exp, int32_t *out_nhyp,
+                         int32_t *out_nkept, int32_t *out_status, void *workspace, size_t ws_bytes,
+                         ctcalign_stream stream);
+
+/* Workspace bytes of ctcalign_beam_decode for N utterances of T[i] frames
+ * (host array) and beam width `beam`; 0 on invalid arguments. */
+size_t ctcalign_beam_workspace_bytes(int32_t N, const int32_t *T, int32_t beam);
+
 /* ---- serving: continuous batching of arriving requests ------------------ */
 
 /* One alignment request.  All pointers are device pointers that must stay

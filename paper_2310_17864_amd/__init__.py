@@ -25,7 +25,7 @@ from . import _lib
 from ._lib import (CtcAlignError, EAGAIN, EBUSY, EDEVICE, EINFEASIBLE, EINVAL, ENOMEM, OK,
                    LibraryMissing, strerror)
 
-__all__ = ["align", "align_checkpointed", "checkpointed_workspace_bytes", "align_noalloc", "token_spans", "align_many_launches", "Context", "Plan", "Server", "workspace_bytes", "strerror",
+__all__ = ["align", "beam_decode", "BeamResult", "align_checkpointed", "checkpointed_workspace_bytes", "align_noalloc", "token_spans", "align_many_launches", "Context", "Plan", "Server", "workspace_bytes", "strerror",
            "CtcAlignError", "LibraryMissing", "OK", "EINVAL", "EINFEASIBLE", "ENOMEM",
            "EDEVICE", "EAGAIN", "EBUSY"]
 
@@ -214,6 +214,63 @@ def checkpointed_workspace_bytes(T: int, L: int, C: int, every: int = 0,
                                  device: Optional[int] = None) -> int:
     return int(_lib.load().ctcalign_checkpointed_workspace_bytes(context(device).handle, T, L, C,
                                                                  int(every)))
+
+
+class BeamResult:
+    """Device outputs of beam_decode (tensors on the probabilities' device)."""
+
+    def __init__(self, tokens, tok_off, T, beam, lengths, logp, scaled, exp2, nhyp, nkept, status):
+        self.tokens, self.tok_off, self.T, self.beam = tokens, tok_off, T, beam
+        self.lengths, self.logp, self.scaled, self.exp2 = lengths, logp, scaled, exp2
+        self.nhyp, self.nkept, self.status = nhyp, nkept, status
+
+    def hypotheses(self, i: int):
+        """Final beam of utterance i as (list of int32 label arrays, float32
+        log-probabilities), in rank order (copies to the host)."""
+        n = int(self.nhyp[i].item())
+        T = int(self.T[i])
+        base = int(self.tok_off[i])
+        toks = self.tokens[base: base + self.beam * T].view(self.beam, T).cpu().numpy()
+        lens = self.lengths[i * self.beam: i * self.beam + n].cpu().numpy()
+        lp = self.logp[i * self.beam: i * self.beam + n].cpu().numpy()
+        return [toks[k, :lens[k]].copy() for k in range(n)], lp
+
+
+def beam_decode(probs, prob_off, T, blank: int = 0, beam: int = 10, threshold: float = 1.0,
+                V: Optional[int] = None):
+    """CTC prefix beam search with blank collapse (ctcalign_beam_decode) over
+    N utterances whose per-frame probabilities sit in one flat float32 device
+    tensor: utterance i has T[i] frames of V classes at element prob_off[i].
+    Asynchronous on the current stream; returns a BeamResult."""
+    torch = _torch()
+    _check_dev_tensor(probs, torch.float32, "probs")
+    dev = probs.device
+    ctx = context(dev.index)
+    Tn = np.ascontiguousarray(T, dtype=np.int32)
+    off = np.ascontiguousarray(prob_off, dtype=np.int64)
+    n = int(Tn.shape[0])
+    if V is None:
+        if probs.dim() != 2 or n != 1:
+            raise ValueError("V is needed for a flat batch")
+        V = int(probs.shape[1])
+    tok_off = np.zeros(n, np.int64)
+    if n:
+        tok_off[1:] = np.cumsum(Tn.astype(np.int64) * beam)[:-1]
+    tokens = torch.zeros(max(int(np.sum(Tn.astype(np.int64))) * beam, 1), dtype=torch.int32, device=dev)
+    lengths = torch.zeros(max(n * beam, 1), dtype=torch.int32, device=dev)
+    logp = torch.empty(max(n * beam, 1), dtype=torch.float32, device=dev)
+    scaled = torch.empty(max(n * beam, 1), dtype=torch.float32, device=dev)
+    exp2 = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    nhyp = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    nkept = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    status = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _lib.check(_lib.load().ctcalign_beam_decode(
+        ctx.handle, n, probs.data_ptr(), ptr(off), ptr(Tn), int(V), int(blank), int(beam),
+        ctypes.c_float(threshold), tokens.data_ptr(), ptr(tok_off), lengths.data_ptr(),
+        logp.data_ptr(), scaled.data_ptr(), exp2.data_ptr(), nhyp.data_ptr(), nkept.data_ptr(),
+        status.data_ptr(), None, 0, _stream_handle(dev)), "beam_decode")
+    return BeamResult(tokens, tok_off, Tn, beam, lengths, logp, scaled, exp2, nhyp, nkept, status)
 
 
 def align_noalloc(emission, labels, blank: int = 0, out=None):

@@ -50,6 +50,9 @@ _PROTOS = {
     "ctcalign_align_checkpointed": (ctypes.c_int, [P, P, I32, I32, P, I32, I32, P, P, P, P, I32,
                                                    P, SZ, P]),
     "ctcalign_checkpointed_workspace_bytes": (SZ, [P, I32, I32, I32, I32]),
+    "ctcalign_beam_decode": (ctypes.c_int, [P, I32, P, P, P, I32, I32, I32, ctypes.c_float, P, P,
+                                            P, P, P, P, P, P, P, P, SZ, P]),
+    "ctcalign_beam_workspace_bytes": (SZ, [I32, P, I32]),
     "ctcalign_align_noalloc": (ctypes.c_int, [P, P, I32, I32, P, I32, I32, P, P, P, P, P]),
     "ctcalign_noalloc_scratch_bytes": (SZ, []),
     "ctcalign_token_spans": (ctypes.c_int, [P, P, I32, I32, I32, P, P, P, P, P, P]),

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libctcalign.so")
 SOURCES = ["k_one.hip", "k_batch.hip", "k_multi.hip", "k_serve.hip", "k_misc.hip",
-           "api.cpp", "server.cpp", "noalloc.hip", "k_ckpt.hip"]
+           "api.cpp", "server.cpp", "noalloc.hip", "k_ckpt.hip", "k_beam.hip"]
 HEADERS = ["engine.hpp", "internal.hpp", "kernels.hpp", "kernels_common.hpp", "tune.hpp", "ctx.hpp",
            "sched.hpp", os.path.join("..", "..", "include", "ctcalign.h")]
 
