@@ -30,11 +30,13 @@
 // 64-bit hash, confirmed by the node identity or, if the nodes differ, a
 // walk up both chains, so equality is exact.
 //
-// Selection per frame: the B stays are B distinct candidates, so the least
-// of their keys bounds the B-th best key from below; only candidates at or
-// above that bound enter an LDS list, from which one wavefront picks the top
-// B by repeated maximum.  If the list overflows, the whole workgroup picks
-// the top B by repeated maximum over all candidates instead.
+// Selection per frame: any B distinct candidates bound the B-th best key
+// from below; the bound is the B-th best among the stays and each
+// hypothesis's extension by the frame's most probable class.  Only
+// candidates at or above it enter an LDS list; the top B are ranked by
+// counting (a short list) or by repeated maximum (a long one); if the list
+// overflows, the whole workgroup picks the top B by repeated maximum over
+// all candidates.
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -122,10 +124,14 @@ struct Shared {
   int child_of[kBMaxB];                 // beam index of h_j's parent prefix, or -1
   uint32_t merged[kBMaxB][kBMaxV / 32]; // (i, c): h_i + c is a beam hypothesis
   uint64_t stay_key[kBMaxB];
+  uint64_t ext_key[kBMaxB];             // extension of h_j by the frame's top class
+  uint64_t rowmax[kBT / 64];
+  uint64_t bound;
   uint64_t list[kBList];
   uint64_t win[kBMaxB];
   uint64_t wmax[2][kBT / 64];
   int cnt, nsel;
+  uint8_t flag[kBT];                    // blank-frame flags of the current 256-frame chunk
 };
 
 // Candidate (i, c) of the current frame: p_b', p_nb' (stays include the
@@ -180,147 +186,249 @@ __global__ void __launch_bounds__(kBT) k_beam(const BeamDesc* __restrict__ descs
   int kept = 0;            // frames kept by blank collapse (all of them, also after a failure)
   bool prev_blank = false;
   const int words = (V + 31) >> 5;
-  __syncthreads();
-  for (int t = 0; t < T; ++t) {
-    const float* yt = d.y + (int64_t)t * V;
-    const bool is_blank = yt[blank] > thr;          // same value in every thread
-    const bool keep = !(is_blank && prev_blank);
-    prev_blank = is_blank;
-    if (!keep) continue;
-    const int ki = kept++;
-    if (status != 0) continue;
-    // (a) the row; merge structure of the current beam
-    for (int c = tid; c < V; c += kBT) sh.row[c] = yt[c];
-    for (int w = tid; w < n * words; w += kBT) sh.merged[w / words][w % words] = 0u;
-    if (tid < n) {
-      int p = -1;
-      for (int i = 0; i < n && p < 0; ++i)
-        if (parent_is(sh.hyp[tid], sh.hyp[i], d.nodes)) p = i;
-      sh.child_of[tid] = p;
-    }
-    if (tid == 0) sh.cnt = 0;
+  // this thread's classes: c = tid + k*256; their probabilities for the
+  // frame being processed, and prefetched for the next kept frame
+  float yv[kBCols], pre[kBCols];
+  int pre_t = -1;
+  for (int t0 = 0; t0 < T; t0 += kBT) {
+    // blank-frame flags of the next 256 frames, read at once
+    const int nt = T - t0 < kBT ? T - t0 : kBT;
+    __syncthreads();   // the previous chunk's flags are no longer read
+    if (tid < nt) sh.flag[tid] = d.y[(int64_t)(t0 + tid) * V + blank] > thr ? 1 : 0;
     __syncthreads();
-    // (b) merged extensions; stay keys
-    if (tid < n) {
-      const int p = sh.child_of[tid];
-      if (p >= 0) {
-        const int c = sh.hyp[tid].last;
-        atomicOr(&sh.merged[p][c >> 5], 1u << (c & 31));
-      }
-      float pb, pnb;
-      cand(sh, tid, blank, blank, pb, pnb);
-      sh.stay_key[tid] = make_key(pb + pnb, tid * V + blank);
-    }
-    __syncthreads();
-    // (c) candidates at or above the bound into the list
-    uint64_t bound = 1ull;
-    if (n == B) {
-      bound = ~0ull;
-      for (int j = 0; j < n; ++j) bound = sh.stay_key[j] < bound ? sh.stay_key[j] : bound;
-      if (bound == 0ull) bound = 1ull;
-    }
-    if (tid < n && sh.stay_key[tid] >= bound) {
-      const int slot = atomicAdd(&sh.cnt, 1);
-      if (slot < kBList) sh.list[slot] = sh.stay_key[tid];
-    }
+    for (int tt = 0; tt < nt; ++tt) {
+      const int t = t0 + tt;
+      const bool is_blank = sh.flag[tt] != 0;
+      const bool keep = !(is_blank && prev_blank);
+      prev_blank = is_blank;
+      if (!keep) continue;
+      const int ki = kept++;
+      if (status != 0) continue;
+      // (a) the row (prefetched when this frame was known in time)
+      if (pre_t == t) {
 #pragma unroll
-    for (int k = 0; k < kBCols; ++k) {
-      const int c = tid + k * kBT;
-      if (c >= V || c == blank) continue;
-      for (int i = 0; i < n; ++i) {
-        float pb, pnb;
-        if (!cand(sh, i, c, blank, pb, pnb)) continue;
-        const uint64_t key = make_key(pb + pnb, i * V + c);
-        if (key >= bound) {
-          const int slot = atomicAdd(&sh.cnt, 1);
-          if (slot < kBList) sh.list[slot] = key;
+        for (int k = 0; k < kBCols; ++k) yv[k] = pre[k];
+      } else {
+        const float* yt = d.y + (int64_t)t * V;
+#pragma unroll
+        for (int k = 0; k < kBCols; ++k) yv[k] = tid + k * kBT < V ? yt[tid + k * kBT] : 0.0f;
+      }
+      // the next kept frame of this chunk, if any: start loading its row
+      {
+        int tn = -1;
+        bool pb_ = is_blank;
+        for (int q = tt + 1; q < nt; ++q) {
+          const bool ib = sh.flag[q] != 0;
+          if (!(ib && pb_)) { tn = t0 + q; break; }
+          pb_ = ib;
+        }
+        pre_t = tn;
+        if (tn >= 0) {
+          const float* yn = d.y + (int64_t)tn * V;
+#pragma unroll
+          for (int k = 0; k < kBCols; ++k) pre[k] = tid + k * kBT < V ? yn[tid + k * kBT] : 0.0f;
         }
       }
-    }
-    __syncthreads();
-    // (d) the B best keys, in order
-    const int cnt = sh.cnt;
-    if (cnt <= kBList) {
+#pragma unroll
+      for (int k = 0; k < kBCols; ++k)
+        if (tid + k * kBT < V) sh.row[tid + k * kBT] = yv[k];
+      // the frame's most probable non-blank class (ties: the smaller class)
+      {
+        uint64_t best = 0ull;
+#pragma unroll
+        for (int k = 0; k < kBCols; ++k) {
+          const int c = tid + k * kBT;
+          if (c < V && c != blank) {
+            const uint64_t key = ((uint64_t)__builtin_bit_cast(uint32_t, yv[k]) << 32) |
+                                 (uint64_t)(0xFFFFFFFFu - (uint32_t)c);
+            best = key > best ? key : best;
+          }
+        }
+        best = wave_max(best);
+        if (lane == 0) sh.rowmax[wv] = best;
+      }
+      for (int w = tid; w < n * words; w += kBT) sh.merged[w / words][w % words] = 0u;
+      if (tid < n) {
+        int p = -1;
+        for (int i = 0; i < n && p < 0; ++i)
+          if (parent_is(sh.hyp[tid], sh.hyp[i], d.nodes)) p = i;
+        sh.child_of[tid] = p;
+      }
+      if (tid == 0) sh.cnt = 0;
+      __syncthreads();
+      // (b) merged extensions; stay keys; the extension of each hypothesis by
+      // the frame's most probable class (unless it joins a stay)
+      if (tid < n) {
+        const int p = sh.child_of[tid];
+        if (p >= 0) {
+          const int c = sh.hyp[tid].last;
+          atomicOr(&sh.merged[p][c >> 5], 1u << (c & 31));
+        }
+        float pb, pnb;
+        cand(sh, tid, blank, blank, pb, pnb);
+        sh.stay_key[tid] = make_key(pb + pnb, tid * V + blank);
+        uint64_t rm = 0ull;
+        for (int w = 0; w < kBT / 64; ++w) rm = sh.rowmax[w] > rm ? sh.rowmax[w] : rm;
+        uint64_t ek = 0ull;
+        if (rm != 0ull) {
+          const int cs = (int)(0xFFFFFFFFu - (uint32_t)rm);
+          bool joins = false;
+          for (int k = 0; k < n; ++k) joins |= sh.child_of[k] == tid && sh.hyp[k].last == cs;
+          if (!joins) {
+            const Hyp& h = sh.hyp[tid];
+            ek = make_key(0.0f + (cs == h.last ? h.pb : h.s) * sh.row[cs], tid * V + cs);
+          }
+        }
+        sh.ext_key[tid] = ek;
+      }
+      __syncthreads();
+      // (b2) the bound: the B-th largest of those (up to) 2n distinct
+      // candidates' keys -- any B distinct candidates bound the B-th best
+      // key from below; 1 (every positive candidate) when there are fewer
       if (wv == 0) {
+        uint64_t key = 0ull;
+        if (lane < n) key = sh.stay_key[lane];
+        else if (lane < 2 * n) key = sh.ext_key[lane - n];
+        int rank = 0, valid = 0;
+        for (int q = 0; q < 2 * n; ++q) {
+          const uint64_t o = q < n ? sh.stay_key[q] : sh.ext_key[q - n];
+          rank += o > key ? 1 : 0;
+          valid += o != 0ull ? 1 : 0;
+        }
+        if (lane == 0 && valid < B) sh.bound = 1ull;
+        if (lane < 2 * n && key != 0ull && rank == B - 1 && valid >= B) sh.bound = key;
+      }
+      __syncthreads();
+      // (c) candidates at or above the bound into the list
+      const uint64_t bound = sh.bound;
+      if (tid < n && sh.stay_key[tid] != 0ull && sh.stay_key[tid] >= bound) {
+        const int slot = atomicAdd(&sh.cnt, 1);
+        if (slot < kBList) sh.list[slot] = sh.stay_key[tid];
+      }
+      // A key at or above the bound needs a total at or above the bound's
+      // float part; float products are monotone, so max(s, p_b) times this
+      // thread's largest probability bounds every extension of a hypothesis
+      // here (exact pruning, no rounding involved).
+      const float bound_f = __builtin_bit_cast(float, (uint32_t)(bound >> 32));
+      float ymax = 0.0f;
+#pragma unroll
+      for (int k = 0; k < kBCols; ++k) {
+        const int c = tid + k * kBT;
+        if (c < V && c != blank) ymax = yv[k] > ymax ? yv[k] : ymax;
+      }
+      for (int i = 0; i < n; ++i) {
+        const Hyp& h = sh.hyp[i];
+        const float hs = h.s, hpb = h.pb;
+        if ((hs > hpb ? hs : hpb) * ymax < bound_f) continue;
+        const int hl = h.last;
+#pragma unroll
+        for (int k = 0; k < kBCols; ++k) {
+          const int c = tid + k * kBT;
+          // extension (i, c): p_b' = 0, p_nb' = x, total 0 + x
+          const float x = (c == hl ? hpb : hs) * yv[k];
+          if (!(x >= bound_f) || c >= V || c == blank) continue;
+          if ((sh.merged[i][c >> 5] >> (c & 31)) & 1u) continue;
+          const uint64_t key = make_key(0.0f + x, i * V + c);
+          if (key >= bound) {
+            const int slot = atomicAdd(&sh.cnt, 1);
+            if (slot < kBList) sh.list[slot] = key;
+          }
+        }
+      }
+      __syncthreads();
+      // (d) the B best keys, in order
+      const int cnt = sh.cnt;
+      if (cnt <= kBT) {
+        // rank of each listed key among the listed keys (all distinct)
+        if (tid < cnt) {
+          const uint64_t key = sh.list[tid];
+          int rank = 0;
+          for (int j = 0; j < cnt; ++j) rank += sh.list[j] > key ? 1 : 0;
+          if (rank < B) sh.win[rank] = key;
+        }
+        if (tid == 0) sh.nsel = cnt < B ? cnt : B;
+      } else if (cnt <= kBList) {
+        if (wv == 0) {
+          uint64_t prev = ~0ull;
+          int m = 0;
+          for (int r = 0; r < B; ++r) {
+            uint64_t best = 0ull;
+            for (int q = lane; q < cnt; q += 64) {
+              const uint64_t k = sh.list[q];
+              if (k < prev && k > best) best = k;
+            }
+            best = wave_max(best);
+            if (best == 0ull) break;
+            if (lane == 0) sh.win[r] = best;
+            prev = best;
+            m = r + 1;
+          }
+          if (lane == 0) sh.nsel = m;
+        }
+      } else {
+        // the list overflowed: repeated maximum over every candidate
         uint64_t prev = ~0ull;
         int m = 0;
         for (int r = 0; r < B; ++r) {
           uint64_t best = 0ull;
-          for (int q = lane; q < cnt; q += 64) {
-            const uint64_t k = sh.list[q];
-            if (k < prev && k > best) best = k;
+          if (tid < n && sh.stay_key[tid] < prev && sh.stay_key[tid] > best) best = sh.stay_key[tid];
+          for (int k = 0; k < kBCols; ++k) {
+            const int c = tid + k * kBT;
+            if (c >= V || c == blank) continue;
+            for (int i = 0; i < n; ++i) {
+              float pb, pnb;
+              if (!cand(sh, i, c, blank, pb, pnb)) continue;
+              const uint64_t key = make_key(pb + pnb, i * V + c);
+              if (key < prev && key > best) best = key;
+            }
           }
           best = wave_max(best);
+          if (lane == 0) sh.wmax[r & 1][wv] = best;
+          __syncthreads();
+          best = 0ull;
+          for (int w = 0; w < kBT / 64; ++w) best = sh.wmax[r & 1][w] > best ? sh.wmax[r & 1][w] : best;
           if (best == 0ull) break;
-          if (lane == 0) sh.win[r] = best;
+          if (tid == 0) sh.win[r] = best;
           prev = best;
           m = r + 1;
         }
-        if (lane == 0) sh.nsel = m;
+        if (tid == 0) sh.nsel = m;
       }
-    } else {
-      // the list overflowed: repeated maximum over every candidate
-      uint64_t prev = ~0ull;
-      int m = 0;
-      for (int r = 0; r < B; ++r) {
-        uint64_t best = 0ull;
-        if (tid < n && sh.stay_key[tid] < prev && sh.stay_key[tid] > best) best = sh.stay_key[tid];
-        for (int k = 0; k < kBCols; ++k) {
-          const int c = tid + k * kBT;
-          if (c >= V || c == blank) continue;
-          for (int i = 0; i < n; ++i) {
-            float pb, pnb;
-            if (!cand(sh, i, c, blank, pb, pnb)) continue;
-            const uint64_t key = make_key(pb + pnb, i * V + c);
-            if (key < prev && key > best) best = key;
-          }
+      __syncthreads();
+      const int nsel = sh.nsel;
+      if (nsel == 0) {   // no candidate with a positive total (uniform)
+        status = 2;
+        continue;
+      }
+      // (e) the next beam, rescaled by the best total's power of two
+      const int e = frexp_exp(__builtin_bit_cast(float, (uint32_t)(sh.win[0] >> 32)));
+      E += e;
+      Hyp nh;
+      if (tid < nsel) {
+        const int idx = key_index(sh.win[tid]);
+        const int i = idx / V, c = idx - i * V;
+        float pb, pnb;
+        cand(sh, i, c, blank, pb, pnb);
+        nh = sh.hyp[i];
+        if (c != blank) {
+          const int node = ki * B + tid;
+          d.nodes[node] = make_int2(nh.node, c);
+          nh.phash = nh.hash;
+          nh.hash = hash_ext(nh.hash, c);
+          nh.pnode = nh.node;
+          nh.node = node;
+          nh.len += 1;
+          nh.last = c;
         }
-        best = wave_max(best);
-        if (lane == 0) sh.wmax[r & 1][wv] = best;
-        __syncthreads();
-        best = 0ull;
-        for (int w = 0; w < kBT / 64; ++w) best = sh.wmax[r & 1][w] > best ? sh.wmax[r & 1][w] : best;
-        if (best == 0ull) break;
-        if (tid == 0) sh.win[r] = best;
-        prev = best;
-        m = r + 1;
+        nh.pb = scale_pow2(pb, -e);
+        nh.pnb = scale_pow2(pnb, -e);
+        nh.s = nh.pb + nh.pnb;
       }
-      if (tid == 0) sh.nsel = m;
+      __syncthreads();
+      if (tid < nsel) sh.hyp[tid] = nh;
+      n = nsel;
+      __syncthreads();   // new beam and its nodes visible to the whole workgroup
     }
-    __syncthreads();
-    const int nsel = sh.nsel;
-    if (nsel == 0) {   // no candidate with a positive total (uniform)
-      status = 2;
-      continue;
-    }
-    // (e) the next beam, rescaled by the best total's power of two
-    const int e = frexp_exp(__builtin_bit_cast(float, (uint32_t)(sh.win[0] >> 32)));
-    E += e;
-    Hyp nh;
-    if (tid < nsel) {
-      const int idx = key_index(sh.win[tid]);
-      const int i = idx / V, c = idx - i * V;
-      float pb, pnb;
-      cand(sh, i, c, blank, pb, pnb);
-      nh = sh.hyp[i];
-      if (c != blank) {
-        const int node = ki * B + tid;
-        d.nodes[node] = make_int2(nh.node, c);
-        nh.phash = nh.hash;
-        nh.hash = hash_ext(nh.hash, c);
-        nh.pnode = nh.node;
-        nh.node = node;
-        nh.len += 1;
-        nh.last = c;
-      }
-      nh.pb = scale_pow2(pb, -e);
-      nh.pnb = scale_pow2(pnb, -e);
-      nh.s = nh.pb + nh.pnb;
-    }
-    __syncthreads();
-    if (tid < nsel) sh.hyp[tid] = nh;
-    n = nsel;
-    __syncthreads();   // new beam and its nodes visible to the whole workgroup
   }
   // outputs: labels by walking each hypothesis's nodes
   const int B0 = u * B;
