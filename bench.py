@@ -169,6 +169,28 @@ def copy_calibration(mb):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persistent_batched4096_traffic.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_persistent_batched4096_counters.txt")
+
+
+def measured_issue():
+    """VALU instructions of one replay (both batched kernels) from the
+    committed counter summary, and the time they take at one wave64
+    instruction per 4 cycles on every SIMD (256 CUs x 4 SIMDs at 2.4 GHz);
+    None when the summary is missing or was taken on other sources."""
+    try:
+        kv = {}
+        with open(COUNTERS_FILE) as fh:
+            for line in fh:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.split("=", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_hash") != kernel_source_hash():
+            return None
+        insts = sum(float(v) for k, v in kv.items() if k.endswith(" SQ_INSTS_VALU"))
+        return {"valu_wave_insts_per_replay": insts,
+                "issue_bound_ms": insts * 4 / (CU * SIMD * CLOCK) * 1e3}
+    except (OSError, ValueError):
+        return None
 TRAFFIC_LONG_FILE = os.path.join(ROOT, "profiles", "k_multi_long90000_traffic.txt")
 
 
@@ -196,6 +218,15 @@ def measured_traffic(path=None):
         return f + w
     except (OSError, KeyError, ValueError):
         return None
+
+
+def _issue(ms):
+    """The replay against its VALU issue bound (committed counters)."""
+    m = measured_issue()
+    if m is None:
+        return None
+    m["frac_of_step"] = m["issue_bound_ms"] / ms
+    return m
 
 
 def run_batched(args):
@@ -285,6 +316,7 @@ def run_batched(args):
                      "bytes_per_launch": bytes_alg},
         "alu": {"achieved_ops_per_s": alu, "peak_ops_per_s": VALU_PEAK_OPS,
                 "frac": alu / VALU_PEAK_OPS, "ops_per_launch": ops_alg},
+        "issue": _issue(ms),
         "cpu_baseline": {"value": F / cpu_s, "unit": "aligned frames/s", "cores": int(ref[4]),
                          "kind": "oracle",
                          "sample": f"the whole batch ({args.n} utterances, {F} frames), "

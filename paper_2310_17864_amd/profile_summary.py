@@ -1,11 +1,20 @@
 """Condenses rocprofv3 output into the short text summaries kept under
 profiles/ (kernel durations, HBM traffic per dispatch).
 
-    python -m paper_2310_17864_amd.profile_summary stats <dir> <out.txt> --command "..."
+    python -m paper_2310_17864_amd.profile_summary stats <dir> <out.txt> --command "..." \
+        [--bench-json <bench stdout>]
     python -m paper_2310_17864_amd.profile_summary traffic <fetch_dir> <write_dir> <out.txt> \
         --copy-bytes N --command "..."
+    python -m paper_2310_17864_amd.profile_summary counters <dir> <out.txt> --command "..." \
+        [--kernel PREFIX]
 
-`stats` reads the kernel_stats.csv of a `--kernel-trace --stats` run.
+`stats` reads the kernel_stats.csv of a `--kernel-trace --stats` run and,
+given the JSON line the profiled bench.py printed, records the step time the
+bench measured itself with HIP events in that same run.
+`counters` reads the counter_collection.csv of a `--pmc` run and records,
+per kernel, the median per-dispatch value of every counter collected, plus
+the ratios the kernel notes use (VALU instructions per active VALU cycle,
+wait share of wave cycles, LDS bank conflicts per LDS instruction).
 `traffic` reads the counter_collection.csv of two `--pmc FETCH_SIZE` /
 `--pmc WRITE_SIZE` runs, takes the median per-dispatch value of the
 persistent alignment kernel and of the calibration copy kernel (an
@@ -41,13 +50,24 @@ def _find(d: str, suffix: str) -> str:
     return hits[0]
 
 
-def stats(d: str, out: str, command: str, top: int = 12) -> None:
+def stats(d: str, out: str, command: str, top: int = 12, bench_json: str = "") -> None:
     rows = list(csv.DictReader(open(_find(d, "kernel_stats.csv"))))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     lines = ["# rocprofv3 --kernel-trace --stats summary",
              f"# command: {command}",
-             f"# kernel sources: {kernel_source_hash()}",
-             f"{'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_%':>8}  kernel"]
+             f"# kernel sources: {kernel_source_hash()}"]
+    if bench_json:
+        import json
+        rec = None
+        for line in open(bench_json):
+            line = line.strip()
+            if line.startswith("{"):
+                rec = json.loads(line)
+        if rec and "ms_per_step" in rec:
+            lines.append(f"# the same run's own step time (HIP events around each graph replay, "
+                         f"{rec.get('steps')} steps): ms_per_step = {rec['ms_per_step']:.4f} "
+                         f"(min {rec.get('ms_min', 0):.4f}, max {rec.get('ms_max', 0):.4f})")
+    lines.append(f"{'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_%':>8}  kernel")
     for r in rows[:top]:
         lines.append(f"{int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
                      f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
@@ -102,6 +122,39 @@ def traffic(fetch_dir: str, write_dir: str, out: str, copy_bytes: int, command: 
     print("\n".join(lines))
 
 
+def counters(d: str, out: str, command: str, kernel: str = "ctca::") -> None:
+    path = _find(d, "counter_collection.csv")
+    per = {}      # (kernel, counter) -> {dispatch: value}
+    for r in csv.DictReader(open(path)):
+        if kernel not in r["Kernel_Name"]:
+            continue
+        k = r["Kernel_Name"].split("(")[0]
+        key = (k, r["Counter_Name"])
+        disp = per.setdefault(key, {})
+        disp[r["Dispatch_Id"]] = disp.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    if not per:
+        raise SystemExit(f"no counter rows for kernels matching {kernel!r} in {path}")
+    lines = ["# rocprofv3 --pmc summary: per-dispatch medians per kernel",
+             f"# command: {command}",
+             f"kernel_source_hash = {kernel_source_hash()}"]
+    kernels = sorted({k for k, _ in per})
+    for k in kernels:
+        vals = {c: statistics.median(v.values()) for (kk, c), v in per.items() if kk == k}
+        n = max(len(v) for (kk, c), v in per.items() if kk == k)
+        lines.append(f"# {k} ({n} dispatches)")
+        for c in sorted(vals):
+            lines.append(f"{k} {c} = {vals[c]:.6g}")
+        def ratio(a, b, label):
+            if a in vals and b in vals and vals[b] > 0:
+                lines.append(f"{k} {label} = {vals[a] / vals[b]:.4f}")
+        ratio("SQ_ACTIVE_INST_VALU", "SQ_INSTS_VALU", "cycles_per_valu_inst")
+        ratio("SQ_WAIT_ANY", "SQ_WAVE_CYCLES", "wait_share_of_wave_cycles")
+        ratio("SQ_LDS_BANK_CONFLICT", "SQ_INSTS_LDS", "lds_conflict_cycles_per_lds_inst")
+        ratio("SQ_INSTS_VALU", "SQ_WAVES", "valu_insts_per_wave")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -109,6 +162,12 @@ def main(argv=None):
     a.add_argument("dir")
     a.add_argument("out")
     a.add_argument("--command", required=True)
+    a.add_argument("--bench-json", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("out")
+    c.add_argument("--command", required=True)
+    c.add_argument("--kernel", default="ctca::")
     b = sub.add_parser("traffic")
     b.add_argument("fetch_dir")
     b.add_argument("write_dir")
@@ -119,7 +178,9 @@ def main(argv=None):
                    help="name prefix of the kernels whose per-dispatch traffic is summed")
     args = ap.parse_args(argv)
     if args.cmd == "stats":
-        stats(args.dir, args.out, args.command)
+        stats(args.dir, args.out, args.command, bench_json=args.bench_json)
+    elif args.cmd == "counters":
+        counters(args.dir, args.out, args.command, kernel=args.kernel)
     else:
         traffic(args.fetch_dir, args.write_dir, args.out, args.copy_bytes, args.command,
                 kernel=args.kernel)
