@@ -639,6 +639,101 @@ def run_decode(args, pk=None):
     return out
 
 
+def run_corun(args, pk_serve):
+    """A resident serving kernel beside a batched plan: the batched replay
+    time alone, the served latency alone, then both at once (replays looping
+    on their own stream in a second host thread while Poisson requests are
+    submitted), so the cost each imposes on the other is measured."""
+    import ctypes
+    import threading
+
+    import torch
+
+    import paper_2310_17864_amd as ca
+    from paper_2310_17864_amd import _lib, synth
+    pk = synth.packed_parallel("batched", args.n, workers=args.gen_workers, t_lo=100, t_hi=6000)
+    dev = torch.device("cuda:0")
+    em = torch.from_numpy(pk["em"]).to(dev)
+    lab = torch.from_numpy(pk["lab"]).to(dev)
+    plan = ca.Plan(em, pk["em_off"], pk["T"], pk["C"], lab, pk["lab_off"], pk["L"], pk["fr_off"], 0)
+    pem = torch.from_numpy(pk_serve["em"]).to(dev)
+    plab = torch.from_numpy(pk_serve["lab"]).to(dev)
+    Tn = pk_serve["T"].astype(np.int64)
+    fr = np.concatenate([[0], np.cumsum(Tn)])
+    paths = torch.empty(int(fr[-1]), dtype=torch.int32, device=dev)
+    scores = torch.empty(int(fr[-1]), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    lib = _lib.load()
+    side = torch.cuda.Stream()
+
+    def replays(n, out):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(n)]
+        for a, b in ev:
+            a.record(side)
+            plan.run(side)
+            b.record(side)
+        side.synchronize()
+        out.extend(a.elapsed_time(b) for a, b in ev)
+
+    def serve(seconds, srv):
+        times, idx = synth.poisson_arrivals(args.rate, seconds, len(Tn), seed=7)
+        tk = ctypes.c_uint64()
+        tickets = []
+        t0 = time.monotonic() + 0.02
+        for k, (a, i) in enumerate(zip(times, idx)):
+            now = time.monotonic()
+            if t0 + a > now:
+                time.sleep(t0 + a - now)
+            i = int(i)
+            req = _lib.Request(pem.data_ptr() + 4 * int(pk_serve["em_off"][i]), int(Tn[i]),
+                               int(pk_serve["C"][i]),
+                               plab.data_ptr() + 4 * int(pk_serve["lab_off"][i]), int(pk_serve["L"][i]),
+                               0, paths.data_ptr() + 4 * int(fr[i]), scores.data_ptr() + 4 * int(fr[i]),
+                               None)
+            _lib.check(lib.ctcalign_server_submit(srv.handle, ctypes.byref(req), ctypes.byref(tk)), "submit")
+            tickets.append(tk.value)
+        st = ctypes.c_int32()
+        tm = _lib.Timing()
+        lat = []
+        for k, t in enumerate(tickets):
+            lib.ctcalign_server_wait(srv.handle, ctypes.c_uint64(t), ctypes.byref(st), ctypes.byref(tm))
+            lat.append(tm.done_s - (t0 + times[k]))
+        lat = np.asarray(lat)
+        return {"requests": len(tickets), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+
+    for _ in range(3):
+        plan.run(side)
+    side.synchronize()
+    alone = []
+    replays(args.steps, alone)
+    srv = ca.Server(args.budget_gb << 30)
+    serve_alone = serve(args.serve_seconds, srv)
+    # both: replays back to back for as long as requests arrive
+    co = []
+    stop = threading.Event()
+
+    def loop():
+        while not stop.is_set():
+            replays(4, co)
+
+    th = threading.Thread(target=loop)
+    th.start()
+    serve_co = serve(args.serve_seconds, srv)
+    stop.set()
+    th.join()
+    srv.close()
+    plan.close()
+    return {"workload": f"batched {args.n} utterances replayed back to back beside Poisson "
+                        f"{args.rate}/s serving for {args.serve_seconds}s (pool {len(Tn)}, T log-uniform "
+                        "100-30000)",
+            "replay_ms_alone": float(np.mean(alone)), "replay_ms_beside_server": float(np.mean(co)),
+            "replays_beside_server": len(co),
+            "serving_alone": serve_alone, "serving_beside_replays": serve_co,
+            "server_workgroups": os.environ.get("CTCALIGN_SERVE_WGS", "one per CU")}
+
+
 def _sub(rec):
     """A sub-record: the workload's own figures without the top-level keys."""
     drop = ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data")
@@ -650,7 +745,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batched", choices=["batched", "long", "single", "serve", "decode"])
+    ap.add_argument("--workload", default="batched",
+                    choices=["batched", "long", "single", "serve", "decode", "corun"])
     ap.add_argument("--decode-n", type=int, default=2048,
                     help="utterances of the beam-search decoding sub-record (0: skip)")
     ap.add_argument("--decode-steps", type=int, default=5)
@@ -680,7 +776,7 @@ def main():
         t = time.time()
         pk_decode = synth.decode_packed(n=args.decode_n, workers=args.gen_workers)
         log(f"decoding workload generated in {time.time() - t:.1f}s")
-    if args.workload == "serve" or (args.workload == "batched" and args.serve_seconds > 0):
+    if args.workload in ("serve", "corun") or (args.workload == "batched" and args.serve_seconds > 0):
         # generated before any GPU work: the generator forks worker processes
         from paper_2310_17864_amd import synth
         t = time.time()
@@ -712,6 +808,8 @@ def main():
         }
     elif args.workload == "serve":
         out = {"metric": METRIC, "serving": run_serving(args, pk_serve)}
+    elif args.workload == "corun":
+        out = {"metric": METRIC, "corun": run_corun(args, pk_serve)}
     elif args.workload == "decode":
         out = {"metric": METRIC, "beam_decode": run_decode(args, pk_decode)}
     else:
