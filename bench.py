@@ -168,6 +168,7 @@ def copy_calibration(mb):
     del a, b
 
 
+TUNED_FILE = os.path.join(ROOT, "paper_2310_17864_amd", "tuned", "mi355x_batched4096.txt")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persistent_batched4096_traffic.txt")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_persistent_batched4096_counters.txt")
 
@@ -249,19 +250,44 @@ def run_batched(args):
     dev = torch.device("cuda:0")
     em = torch.from_numpy(pk["em"]).to(dev)
     lab = torch.from_numpy(pk["lab"]).to(dev)
-    plan = ca.Plan(em, pk["em_off"], pk["T"], pk["C"], lab, pk["lab_off"], pk["L"],
-                   pk["fr_off"], 0)
-    wall, per = time_graph(plan, args.steps, args.warmup)
     F = int(pk["frames"])
-    ms = float(np.mean(per))
-    st = plan.status.cpu().numpy()[: plan.n]
-    paths = plan.paths.cpu().numpy()[:F]
-    scores = plan.scores.cpu().numpy()[:F]
-    totals = plan.totals.cpu().numpy()[: plan.n]
     ok = ref[0] == 0
-    exact = bool(np.array_equal(st, ref[0]) and np.array_equal(paths, ref[1])
-                 and np.array_equal(scores.view(np.uint32), ref[2].view(np.uint32))
-                 and np.array_equal(totals[ok].view(np.uint32), ref[3][ok].view(np.uint32)))
+
+    def exact_of(plan):
+        st = plan.status.cpu().numpy()[: plan.n]
+        paths = plan.paths.cpu().numpy()[:F]
+        scores = plan.scores.cpu().numpy()[:F]
+        totals = plan.totals.cpu().numpy()[: plan.n]
+        return (bool(np.array_equal(st, ref[0]) and np.array_equal(paths, ref[1])
+                     and np.array_equal(scores.view(np.uint32), ref[2].view(np.uint32))
+                     and np.array_equal(totals[ok].view(np.uint32), ref[3][ok].view(np.uint32))),
+                st, paths, scores, totals)
+
+    # the cost model's table, then the committed table tuned on this workload
+    # (the timed figure is the tuned one when the table is there)
+    tuning = {"table": None}
+    exact0 = True
+    if not args.only_tuned:
+        plan0 = ca.Plan(em, pk["em_off"], pk["T"], pk["C"], lab, pk["lab_off"], pk["L"], pk["fr_off"], 0)
+        wall0, per0 = time_graph(plan0, args.steps, args.warmup)
+        exact0 = exact_of(plan0)[0]
+        plan0.close()
+        tuning.update(ms_per_step_cost_model=float(np.mean(per0)), bit_exact_cost_model=exact0)
+    if os.path.exists(TUNED_FILE) and not args.no_tuned:
+        tctx = ca.Context(0)
+        tctx.tune_load(TUNED_FILE)
+        plan = ca.Plan(em, pk["em_off"], pk["T"], pk["C"], lab, pk["lab_off"], pk["L"], pk["fr_off"], 0,
+                       ctx=tctx)
+        wall, per = time_graph(plan, args.steps, args.warmup)
+        tuning["table"] = os.path.relpath(TUNED_FILE, ROOT)
+        tuning["knobs"] = {k: tctx.tune_knob(k) for k in ("pack_target_m", "crit_frac", "crit_per_cu")}
+        tuning["ms_per_step_tuned"] = float(np.mean(per))
+    else:
+        plan = ca.Plan(em, pk["em_off"], pk["T"], pk["C"], lab, pk["lab_off"], pk["L"], pk["fr_off"], 0)
+        wall, per = time_graph(plan, args.steps, args.warmup)
+    ms = float(np.mean(per))
+    exact, st, paths, scores, totals = exact_of(plan)
+    exact = exact and exact0
     mismatch = None
     if not exact:
         bad = []
@@ -304,6 +330,7 @@ def run_batched(args):
                    "utterances": args.n, "frames": F, "state_steps": int(np.sum(
                        pk["T"].astype(np.int64) * (2 * pk["L"].astype(np.int64) + 1)))},
         "bit_exact": exact,
+        "tuning": tuning,
         "mismatch": mismatch,
         "wall_s_timed": wall,
         "ms_min": float(np.min(per)), "ms_max": float(np.max(per)),
@@ -752,6 +779,10 @@ def main():
     ap.add_argument("--decode-steps", type=int, default=5)
     ap.add_argument("--n", type=int, default=4096, help="utterances in the batched workload")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tuned", action="store_true",
+                    help="time only the cost model's table, not the committed tuned table")
+    ap.add_argument("--only-tuned", action="store_true",
+                    help="time only the committed tuned table (profiling runs)")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the single (T=200) and long-form (T=90,000) sub-records")
     ap.add_argument("--serve-seconds", type=float, default=60.0,

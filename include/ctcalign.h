@@ -114,9 +114,27 @@ int ctcalign_tune_set(ctcalign_ctx *ctx, int32_t kind, int32_t s_lo, int32_t s_h
 int ctcalign_tune_get(ctcalign_ctx *ctx, int32_t kind, int32_t S, int32_t C, int32_t *W,
                       int32_t *M);
 
-/* Writes / reads the table as text lines "kind class bucket W M" (host file
- * path).  ctcalign_ctx_create loads $CTCALIGN_TUNE_CACHE when it is set.
- * Entries the kernels cannot run are skipped (EINVAL is returned). */
+/* Scheduling knobs of the batched plan, tuned on a whole workload
+ * (paper_2310_17864_amd/tune.py --workload):
+ *   PACK_TARGET_M  states per lane the pack kernel aims for (2..16; more
+ *                  states per lane: fewer waves, longer frames)
+ *   CRIT_FRAC      alignments whose modelled chain time is within this
+ *                  fraction of the longest run as critical chains on their
+ *                  own 8-wave workgroups (0 disables; 0..1)
+ *   CRIT_PER_CU    at most this many critical chains per compute unit (0..4)
+ * Plans created afterwards use the new value; *previous (nullable) receives
+ * the old one.  EINVAL for an unknown knob or a value out of range. */
+enum {
+  CTCALIGN_KNOB_PACK_TARGET_M = 1,
+  CTCALIGN_KNOB_CRIT_FRAC = 2,
+  CTCALIGN_KNOB_CRIT_PER_CU = 3
+};
+int ctcalign_tune_knob(ctcalign_ctx *ctx, int32_t knob, double value, double *previous);
+
+/* Writes / reads the table as text lines "kind class bucket W M" and
+ * "knob id value" (host file path).  ctcalign_ctx_create loads
+ * $CTCALIGN_TUNE_CACHE when it is set.  Entries the kernels cannot run are
+ * skipped (EINVAL is returned). */
 int ctcalign_tune_save(ctcalign_ctx *ctx, const char *path);
 int ctcalign_tune_load(ctcalign_ctx *ctx, const char *path);
 

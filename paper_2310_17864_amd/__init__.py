@@ -108,6 +108,21 @@ class Context:
                                                  ctypes.byref(M)), "tune_get")
         return int(W.value), int(M.value)
 
+    KNOBS = {"pack_target_m": 1, "crit_frac": 2, "crit_per_cu": 3}
+
+    def tune_knob(self, name: str, value: Optional[float] = None) -> float:
+        """Sets a scheduling knob of batched plans (ctcalign_tune_knob) and
+        returns its previous value; value=None only reads it."""
+        prev = ctypes.c_double()
+        lib = _lib.load()
+        k = self.KNOBS[name]
+        if value is None:
+            lib.ctcalign_tune_knob(self.handle, k, -1.0, ctypes.byref(prev))
+            return float(prev.value)
+        _lib.check(lib.ctcalign_tune_knob(self.handle, k, float(value), ctypes.byref(prev)),
+                   "tune_knob")
+        return float(prev.value)
+
     def tune_save(self, path: str):
         _lib.check(_lib.load().ctcalign_tune_save(self.handle, path.encode()), "tune_save")
 

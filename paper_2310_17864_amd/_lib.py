@@ -64,6 +64,7 @@ _PROTOS = {
     "ctcalign_align_batched": (ctypes.c_int, [P, I32, P, P, P, P, P, P, P, I32, P, P, P, P, P, P]),
     "ctcalign_tune_set": (ctypes.c_int, [P, I32, I32, I32, I32, I32, I32]),
     "ctcalign_tune_get": (ctypes.c_int, [P, I32, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+    "ctcalign_tune_knob": (ctypes.c_int, [P, I32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     "ctcalign_tune_save": (ctypes.c_int, [P, ctypes.c_char_p]),
     "ctcalign_tune_load": (ctypes.c_int, [P, ctypes.c_char_p]),
     "ctcalign_server_create": (ctypes.c_int, [P, SZ, I32, ctypes.POINTER(P)]),

@@ -256,11 +256,38 @@ int ctcalign_tune_get(ctcalign_ctx* ctx, int32_t kind, int32_t S, int32_t C, int
   return g.W > 0 ? CTCALIGN_OK : CTCALIGN_EINVAL;
 }
 
+int ctcalign_tune_knob(ctcalign_ctx* ctx, int32_t knob, double value, double* previous) {
+  if (!ctx) return CTCALIGN_EINVAL;
+  TuneTable& t = ctx->tune;
+  switch (knob) {
+    case CTCALIGN_KNOB_PACK_TARGET_M:
+      if (previous) *previous = t.pack_target_m;
+      if (value < 2 || value > 16) return CTCALIGN_EINVAL;
+      t.pack_target_m = (int)value;
+      return CTCALIGN_OK;
+    case CTCALIGN_KNOB_CRIT_FRAC:
+      if (previous) *previous = t.crit_frac;
+      if (!(value >= 0.0 && value <= 1.0)) return CTCALIGN_EINVAL;
+      t.crit_frac = value;
+      return CTCALIGN_OK;
+    case CTCALIGN_KNOB_CRIT_PER_CU:
+      if (previous) *previous = t.crit_per_cu;
+      if (!(value >= 0.0 && value <= 4.0)) return CTCALIGN_EINVAL;
+      t.crit_per_cu = value;
+      return CTCALIGN_OK;
+    default:
+      return CTCALIGN_EINVAL;
+  }
+}
+
 int ctcalign_tune_save(ctcalign_ctx* ctx, const char* path) {
   if (!ctx || !path) return CTCALIGN_EINVAL;
   FILE* f = std::fopen(path, "w");
   if (!f) return CTCALIGN_EINVAL;
-  std::fprintf(f, "# libctcalign tuning table v1: kind class bucket W M\n");
+  std::fprintf(f, "# libctcalign tuning table v2: kind class bucket W M; knob id value\n");
+  std::fprintf(f, "knob %d %d\n", (int)CTCALIGN_KNOB_PACK_TARGET_M, ctx->tune.pack_target_m);
+  std::fprintf(f, "knob %d %.17g\n", (int)CTCALIGN_KNOB_CRIT_FRAC, ctx->tune.crit_frac);
+  std::fprintf(f, "knob %d %.17g\n", (int)CTCALIGN_KNOB_CRIT_PER_CU, ctx->tune.crit_per_cu);
   for (int kind = 0; kind < 2; ++kind)
     for (int c = 0; c < 2; ++c) {
       const auto& t = kind == 0 ? ctx->tune.one_override[c] : ctx->tune.pack_override[c];
@@ -279,6 +306,12 @@ int ctcalign_tune_load(ctcalign_ctx* ctx, const char* path) {
   int rc = CTCALIGN_OK;
   while (std::fgets(line, sizeof line, f)) {
     if (line[0] == '#') continue;
+    int knob;
+    double kv;
+    if (std::sscanf(line, "knob %d %lf", &knob, &kv) == 2) {
+      if (ctcalign_tune_knob(ctx, knob, kv, nullptr) != CTCALIGN_OK) rc = CTCALIGN_EINVAL;
+      continue;
+    }
     int kind, c, b, W, M;
     if (std::sscanf(line, "%d %d %d %d %d", &kind, &c, &b, &W, &M) != 5) continue;
     if ((kind != 0 && kind != 1) || (c != 0 && c != 1) || b < 0 || b > kMaxS / kWave) {

@@ -1,16 +1,28 @@
-"""Autotuner for the geometry table (waves per alignment W, states per lane M).
+"""Autotuner for the geometry table and the batched plan's scheduling knobs.
 
-For each sampled trellis size S and class count C it times every geometry the
-kernels compile that can hold S, on synthetic emissions, and writes the
-fastest into the context's table (ctcalign_tune_set) for the S range between
-the neighbouring samples; the table can be saved and later loaded through
-$CTCALIGN_TUNE_CACHE.
+Per size: for each sampled trellis size S and class count C it times every
+geometry (waves per alignment W, states per lane M) the kernels compile that
+can hold S, on synthetic emissions, and writes the fastest into the
+context's table (ctcalign_tune_set) for the S range between the neighbouring
+samples.
 
 * kind 0 (single launches): objective = latency of one alignment.
 * kind 1 (batched persistent kernel): objective = time of a batch of
   `batch` alignments of that size through one plan.
 
-    python -m paper_2310_17864_amd.tune --out tune.txt
+Per workload (--workload batched): the plan's scheduling knobs
+(ctcalign_tune_knob: the packs' states-per-lane target, the share of
+critical chains and their density per compute unit) are searched on the
+batched workload itself, timing a graph replay of one plan per setting.
+
+The table (geometry lines and knob lines) is saved with ctcalign_tune_save
+and loaded with ctcalign_tune_load or $CTCALIGN_TUNE_CACHE.  The emission
+ring depth is not a tuned parameter: measured, the row copies do not bound a
+frame (removing their waits changes nothing), and a deeper ring only takes
+LDS.
+
+    python -m paper_2310_17864_amd.tune --out tune.txt            # per size
+    python -m paper_2310_17864_amd.tune --workload batched --out t.txt
 """
 from __future__ import annotations
 
@@ -137,19 +149,80 @@ def apply(ctx, kind: int, C: int, best: Dict[int, Tuple[int, int, float]]) -> Li
     return applied
 
 
+KNOB_GRID = {
+    "pack_target_m": (8, 10, 12, 14, 16),
+    "crit_frac": (0.0, 0.4, 0.5, 0.6, 0.7, 0.8),
+    "crit_per_cu": (0.5, 1.0, 1.5),
+}
+
+
+def tune_workload(ctx, pk: dict, grid=None, reps: int = 3, log=print):
+    """Searches the plan knobs on a packed batch (synth.pack layout): one plan
+    per setting, the median of `reps` graph replays each.  Leaves the best
+    setting in the context and returns (best {knob: value}, best ms,
+    default ms, [(ms, setting), ...])."""
+    import itertools
+
+    import torch
+
+    from . import Plan
+    grid = grid or KNOB_GRID
+    dev = torch.device("cuda", ctx.device)
+    em = torch.from_numpy(pk["em"]).to(dev)
+    lab = torch.from_numpy(pk["lab"]).to(dev)
+    default = {k: ctx.tune_knob(k) for k in grid}
+    names = list(grid)
+    settings = []
+    for combo in itertools.product(*(grid[k] for k in names)):
+        st = dict(zip(names, combo))
+        if st.get("crit_frac", 1.0) == 0.0 and "crit_per_cu" in st and st["crit_per_cu"] != grid["crit_per_cu"][0]:
+            continue          # without critical chains their density does not matter
+        settings.append(st)
+    if default not in settings:
+        settings.append(default)
+    results = []
+    for st in settings:
+        for k, v in st.items():
+            ctx.tune_knob(k, v)
+        plan = Plan(em, pk["em_off"], pk["T"], pk["C"], lab, pk["lab_off"], pk["L"], pk["fr_off"], 0,
+                    ctx=ctx)
+        ms = _time(plan.run, reps)
+        plan.close()
+        results.append((ms, st))
+        log(f"workload knobs {st}: {ms:.3f} ms")
+    results.sort(key=lambda r: r[0])
+    best_ms, best = results[0]
+    default_ms = next(ms for ms, st in results if st == default)
+    for k, v in best.items():
+        ctx.tune_knob(k, v)
+    return best, best_ms, default_ms, results
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default="ctcalign_tune.txt")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--workload", default="", choices=["", "batched"],
+                    help="search the plan knobs on this workload instead of per-size geometries")
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--gen-workers", type=int, default=8)
     args = ap.parse_args(argv)
-    from . import context
-    ctx = context(0)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     t0 = time.time()
-    for C in (32, 256):
-        apply(ctx, 0, C, tune_single(ctx, C, args.reps, log=log))
-        apply(ctx, 1, C, tune_pack(ctx, C, args.batch, args.reps, log=log))
+    if args.workload == "batched":
+        from . import synth
+        pk = synth.packed_parallel("batched", args.n, workers=args.gen_workers, t_lo=100, t_hi=6000)
+        from . import context
+        ctx = context(0)
+        best, best_ms, default_ms, _ = tune_workload(ctx, pk, reps=args.reps, log=log)
+        log(f"best {best}: {best_ms:.3f} ms (defaults {default_ms:.3f} ms)")
+    else:
+        from . import context
+        ctx = context(0)
+        for C in (32, 256):
+            apply(ctx, 0, C, tune_single(ctx, C, args.reps, log=log))
+            apply(ctx, 1, C, tune_pack(ctx, C, args.batch, args.reps, log=log))
     ctx.tune_save(args.out)
     log(f"tuning table written to {args.out} in {time.time() - t0:.0f}s")
 
