@@ -16,12 +16,15 @@
 // through a small LDS ring guarded by counters, so segments never meet at a
 // barrier: segment w may run up to a few 32-frame blocks behind segment w-1.
 //
-// Per frame and state the work is one compare + one select for a blank state
-// and two compares + two selects for a label state, one float add each, plus
-// one v_addc_co_u32 per backpointer bit: the compare's lane mask is shifted
-// straight into a per-lane 32-frame word ("moved one state" plane for every
-// state, "skipped a state" plane for label states), so backpointers cost 1.5
-// bits per state and frame and are stored with coalesced dword stores.
+// Per frame, a blank state and the label state above it share their work:
+// the blank's compare and select pick the better of the two states below the
+// label (ties to the nearer one), which is also the label's best way in from
+// below when it may skip, so the label adds one bitwise select (its skip
+// permission), one compare and one select.  Each state then takes one float
+// add and one v_addc_co_u32: the compare's lane mask is shifted straight into
+// a per-lane 32-frame word, so backpointers cost one bit per state and frame
+// (a label's choice between s-1 and s-2 is the blank's bit of the same frame)
+// and are stored with coalesced dword stores.
 //
 // Emission rows reach LDS in chunks of 4 rows by direct global->LDS loads,
 // one chunk ahead; label states then read their class column from a ring of
@@ -95,42 +98,44 @@ __device__ __forceinline__ bool wait_geq(int* p, int need) {
 
 // ---- one frame of the recurrence for a lane's M states ---------------------
 //
-// a[j] holds a_{t-1} for state sbase+j on entry and a_t on exit.  States are
-// updated from the top down so every read sees a_{t-1}.  nb is a_{t-1} of the
-// state just below this lane's first one.  Even slots are blank states.
-// Skip permission of label slot jj: a per-lane additive penalty (0 or -inf)
-// folded into the compared value -- the compare result is that of the masked
-// compare and the selected value stays the unmodified a_{t-1}(s-2).  (A lane
-// mask ANDed by the scalar unit costs fewer VALU issues but puts a VALU ->
-// SALU -> VALU round trip into every label state's chain: the per-frame
-// latency of one wave measured ~15 % higher.)
+// a[j] holds a_{t-1} for state sbase+j on entry and a_t on exit.  Slot pairs
+// (blank 2p, label 2p+1) are updated from the top down so every read sees
+// a_{t-1}.  nb is a_{t-1} of the state just below this lane's first one.
+// With x = a(s), y = a(s-1), z = a(s-2) for label s, the strict rule picks
+// s-2 iff z > y and z > x, s-1 iff y >= z and y > x, else s; the blank s-1
+// has already compared z with y (its own s-1 and s), so the label compares
+// x with the blank's winner only.  A label that may not skip compares with y
+// alone: its permission is a per-lane all-ones / zero word kb[p] that picks
+// the blank's winner or y bit by bit (v_bfi_b32, no scalar-unit round trip).
+
+// (k & x) | (~k & y) per lane: one v_bfi_b32.
+__device__ __forceinline__ float bitsel(uint32_t k, float x, float y) {
+  float r;
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(k), "v"(x), "v"(y));
+  return r;
+}
 
 template <int M>
 __device__ __forceinline__ void dp_frame(float (&a)[M], uint32_t (&acc)[bp_words_per_lane(M)],
-                                         const float (&skip)[M / 2], float nbs,
+                                         const uint32_t (&kb)[M / 2], float nbs,
                                          float nb_in, float eb, const float (&e)[M / 2]) {
-  // lane 0 takes the boundary value from below; selected only where the two
-  // lowest states use it, so its LDS read may still be in flight until then
+  // lane 0 takes the boundary value from below; selected only where the
+  // lowest pair uses it, so its LDS read may still be in flight until then
   const float nb = sel(1ull, nb_in, nbs);
 #pragma unroll
-  for (int j = M - 1; j >= 0; --j) {
-    const float p1 = (j >= 1) ? a[j - 1] : nb;
-    if (j % 2 == 0) {
-      const uint64_t c1 = gt_mask(p1, a[j]);
-      const float best = sel(c1, p1, a[j]);
-      acc[plane_word(M, plane_mv(M, j))] = shift_in(acc[plane_word(M, plane_mv(M, j))], c1);
-      a[j] = eb + best;
-    } else {
-      const float p2 = (j >= 2) ? a[j - 2] : nb;
-      const uint64_t c1 = gt_mask(p1, a[j]);
-      const float b1 = sel(c1, p1, a[j]);
-      const uint64_t c2 = gt_mask(p2 + skip[j / 2], b1);
-      const float b2 = sel(c2, p2, b1);
-      // moved before skipped: planes are numbered in shift-in order
-      acc[plane_word(M, plane_mv(M, j))] = shift_in(acc[plane_word(M, plane_mv(M, j))], c1);
-      acc[plane_word(M, plane_sk(M, j))] = shift_in(acc[plane_word(M, plane_sk(M, j))], c2);
-      a[j] = e[j / 2] + b2;
-    }
+  for (int p = M / 2 - 1; p >= 0; --p) {
+    const int jb = 2 * p, jl = 2 * p + 1;
+    const float y = a[jb];
+    const float z = (jb >= 1) ? a[jb - 1] : nb;
+    const uint64_t cb = gt_mask(z, y);          // blank: came from below
+    const float wb = sel(cb, z, y);             // the better of z, y
+    const float from_below = bitsel(kb[p], wb, y);
+    const uint64_t cl = gt_mask(from_below, a[jl]);   // label: came from below
+    const float wl = sel(cl, from_below, a[jl]);
+    acc[plane_word(M, plane_of(M, jl))] = shift_in(acc[plane_word(M, plane_of(M, jl))], cl);
+    acc[plane_word(M, plane_of(M, jb))] = shift_in(acc[plane_word(M, plane_of(M, jb))], cb);
+    a[jl] = e[p] + wl;
+    a[jb] = eb + wb;
   }
 }
 
@@ -302,7 +307,7 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   // ring at byte offset 4*label; padding states (s >= S) read the blank
   // column and can neither skip nor feed a real state.
   int eoff[M / 2];
-  float skip[M / 2];   // 0: may enter from two states below, -inf: may not
+  uint32_t skip[M / 2];   // all ones: may enter from two states below, 0: may not
 #pragma unroll
   for (int jj = 0; jj < M / 2; ++jj) {
     const int s = sbase + 2 * jj + 1;
@@ -313,7 +318,7 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
       if (s >= 3) sk = lab != in.lab[(s - 3) / 2];
     }
     eoff[jj] = lab;
-    skip[jj] = sk ? 0.0f : neg_inf();
+    skip[jj] = sk ? ~0u : 0u;
   }
 
   // a3: frame 0.  Only states 0 and 1 start finite.  (A checkpointed
@@ -604,15 +609,17 @@ __device__ __forceinline__ bool prologue_check(const Inst& in, int w, int lane) 
 // The chase s_{t-1} = s_t - k_t(s_t) runs in scalar registers, 32 frames per
 // block.  Over one block the state drops by at most 62, so the block's codes
 // for the 63 states at and below the block's top state sit one per lane (the
-// "band"), each as two 32-frame words (moved, skipped) with frame i of the
-// block at bit 31-i; a frame then costs two readlanes.  Lane i records the
-// state of the block's frame i; its label is fetched after the chase and
-// stored one block later.
+// "band"), each as two 32-frame words with frame i of the block at bit 31-i:
+// the state's own bit and, for a label state that may skip, the bit of the
+// blank state below it (which of the two states below the label came from);
+// a frame then costs two readlanes.  Lane i records the state of the block's
+// frame i; its label is fetched after the chase and stored one block later.
 //
 // Fetches run two blocks ahead: at the top of block b (state e_b) the raw
 // words of block b-2 are requested for the 192 states below e_b (three
-// 64-state windows; the top of block b-2 is at most 124 below e_b).  After
-// block b-1's chase has fixed that top, the windows are realigned to it with
+// 64-state windows; the top of block b-2 is at most 124 below e_b), with the
+// two labels that decide each label state's skip permission.  After block
+// b-1's chase has fixed that top, the windows are realigned to it with
 // ds_bpermute and only the 64-state band is unpacked.  Every fetch is issued
 // unconditionally (clamped addresses; masking happens at unpack time, since
 // overwriting a register with a load in flight would wait for it), so the
@@ -644,17 +651,21 @@ __device__ __forceinline__ Band make_band(uint32_t mv, uint32_t sk) {
   return Band{(spread16(sk >> 16) << 1) | spread16(lo >> 16), (spread16(sk) << 1) | spread16(lo)};
 }
 
-// Raw backpointer words (moved-plane word, skipped-plane word) of one state
-// for the 4 groups of a block.
+// Raw backpointer words of one state for the 4 groups of a block: the word
+// holding its own plane and the word holding the plane of the blank below it
+// (label states; blank states load their own word twice), plus the two labels
+// whose difference is a label state's skip permission (label 0 twice for
+// other states).
 struct RawWin {
   uint32_t wm[4], ws[4];
+  int32_t la, lb;
 };
 
-// Where state q's planes sit in a lane's words.
+// Where state q's plane and its partner's sit in a lane's words.
 struct PlaneLoc {
   int wseg, ln;          // segment, lane
-  int qm, pm, rm;        // moved plane: word, bit offset, planes in the word
-  int qs, ps, rs;        // skipped plane (label slots; blank slots repeat the moved one)
+  int qm, pm, rm;        // own plane: word, bit offset, planes in the word
+  int qs, ps, rs;        // plane of the blank below (label slots; blank slots repeat their own)
   bool odd;
 };
 
@@ -667,19 +678,21 @@ __device__ __forceinline__ PlaneLoc plane_loc(int q) {
   p.ln = rr / M;
   const int j = rr - p.ln * M;
   p.odd = j % 2;
-  const int pmv = plane_mv(M, j);
-  const int psk = p.odd ? plane_sk(M, j) : pmv;
-  p.qm = plane_word(M, pmv);
-  p.pm = plane_pos(M, pmv);
+  const int pown = plane_of(M, j);
+  const int pblk = p.odd ? plane_of(M, j - 1) : pown;   // the blank of the pair sits in the same lane
+  p.qm = plane_word(M, pown);
+  p.pm = plane_pos(M, pown);
   p.rm = planes_in_word(M, p.qm);
-  p.qs = plane_word(M, psk);
-  p.ps = plane_pos(M, psk);
+  p.qs = plane_word(M, pblk);
+  p.ps = plane_pos(M, pblk);
   p.rs = planes_in_word(M, p.qs);
   return p;
 }
 
+// labp: the labels (any readable int32 array when there are none: only
+// state 0 then exists and reads index 0).
 template <int M>
-__device__ __forceinline__ RawWin load_win(const Inst& in, int blk, int ngrp, int q) {
+__device__ __forceinline__ RawWin load_win(const Inst& in, const int* labp, int blk, int ngrp, int q) {
   RawWin r;
   constexpr int NQ = bp_words_per_lane(M);
   const PlaneLoc p = plane_loc<M>(q > 0 ? q : 0);
@@ -692,6 +705,9 @@ __device__ __forceinline__ RawWin load_win(const Inst& in, int blk, int ngrp, in
     r.wm[g] = gb[p.qm * kWave];
     r.ws[g] = gb[p.qs * kWave];
   }
+  const bool lab2 = (q >= 3) && (q % 2);          // a label state with a label two below
+  r.la = labp[lab2 ? (q - 1) / 2 : 0];
+  r.lb = labp[lab2 ? (q - 3) / 2 : 0];
   return r;
 }
 
@@ -713,6 +729,18 @@ __device__ __forceinline__ uint32_t bperm(uint32_t v, int src_lane) {
   return (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane * 4, (int)v);
 }
 
+// Band of state q from its own plane's and its blank partner's 32 frame bits
+// and the two labels fetched for it: a label state came from s-2 where it
+// came from below, may skip, and the blank below came from below too.
+template <int M>
+__device__ __forceinline__ Band band_from(uint32_t mv, uint32_t pb, int32_t la, int32_t lb, int q,
+                                          const PlaneLoc& p) {
+  if (q < 0) mv = 0u;
+  const bool may_skip = q >= 3 && p.odd && la != lb;
+  const uint32_t sk = may_skip ? (mv & pb) : 0u;
+  return make_band(mv, sk);
+}
+
 // Band of state q (= the windows' top - d - lane) from three windows: realign
 // with ds_bpermute and unpack, group by group.
 template <int M>
@@ -725,30 +753,28 @@ __device__ __forceinline__ Band band_of(const RawWin& a, const RawWin& b, const 
     return k == 0 ? ra : (k == 1 ? rb : rc);
   };
   const PlaneLoc p = plane_loc<M>(q > 0 ? q : 0);
-  uint32_t mv = 0u, sk = 0u;
+  uint32_t mv = 0u, pb = 0u;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     mv |= gather8(pick(a.wm[g], b.wm[g], c.wm[g]), p.rm, p.pm) >> (kUnroll * g);
-    sk |= gather8(pick(a.ws[g], b.ws[g], c.ws[g]), p.rs, p.ps) >> (kUnroll * g);
+    pb |= gather8(pick(a.ws[g], b.ws[g], c.ws[g]), p.rs, p.ps) >> (kUnroll * g);
   }
-  if (q < 0) mv = 0u;
-  if (q < 0 || !p.odd) sk = 0u;
-  return make_band(mv, sk);
+  // only whether the two labels differ matters
+  const uint32_t dl = pick((uint32_t)(a.la ^ a.lb), (uint32_t)(b.la ^ b.lb), (uint32_t)(c.la ^ c.lb));
+  return band_from<M>(mv, pb, (int32_t)dl, 0, q, p);
 }
 
 // Band of state q straight from one window (no realignment).
 template <int M>
 __device__ __forceinline__ Band band_direct(const RawWin& a, int q) {
   const PlaneLoc p = plane_loc<M>(q > 0 ? q : 0);
-  uint32_t mv = 0u, sk = 0u;
+  uint32_t mv = 0u, pb = 0u;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     mv |= gather8(a.wm[g], p.rm, p.pm) >> (kUnroll * g);
-    sk |= gather8(a.ws[g], p.rs, p.ps) >> (kUnroll * g);
+    pb |= gather8(a.ws[g], p.rs, p.ps) >> (kUnroll * g);
   }
-  if (q < 0) mv = 0u;
-  if (q < 0 || !p.odd) sk = 0u;
-  return make_band(mv, sk);
+  return band_from<M>(mv, pb, a.la, a.lb, q, p);
 }
 
 // f(integral_constant<N-1>), ..., f(integral_constant<0>)
@@ -794,7 +820,7 @@ __device__ __forceinline__ void backtrack(const Inst& in, const FwdOut& fo, int 
     const int nblk = (T - 1 + kBlk - 1) / kBlk;
     const int ngrp = (int)bp_groups(T);
     // with no labels every state is blank: the label reads hit path[0]
-    const int* labp = in.lab ? in.lab : in.path;
+    const int* labp = (in.L > 0 && in.lab) ? in.lab : in.path;
     int e = fo.send;                       // state at the top of the current block
     Band cur{0u, 0u};
     // Two window sets alternate between "fetched for the block after next"
@@ -803,10 +829,10 @@ __device__ __forceinline__ void backtrack(const Inst& in, const FwdOut& fo, int 
     RawWin setA[3], setB[3];
     int ntop = e;                          // top the next block's windows were fetched below
     if (nblk > 0) {
-      cur = band_direct<M>(load_win<M>(in, nblk - 1, ngrp, e - lane), e - lane);
+      cur = band_direct<M>(load_win<M>(in, labp, nblk - 1, ngrp, e - lane), e - lane);
       const int nb = nblk - 2 >= 0 ? nblk - 2 : 0;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) setA[k] = load_win<M>(in, nb, ngrp, e - k * kWave - lane);
+      for (int k = 0; k < 3; ++k) setA[k] = load_win<M>(in, labp, nb, ngrp, e - k * kWave - lane);
       // enter the loop with no load in flight: the compiler's waits at the
       // loop head then only see the loop's own (exactly counted) fetches
       __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
@@ -823,7 +849,7 @@ __device__ __forceinline__ void backtrack(const Inst& in, const FwdOut& fo, int 
       const int fb = b - 2 >= 0 ? b - 2 : 0;   // for b < 2 the fetch is unused
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        fetch[k] = load_win<M>(in, fb, ngrp, top - k * kWave - lane);
+        fetch[k] = load_win<M>(in, labp, fb, ngrp, top - k * kWave - lane);
         __builtin_amdgcn_sched_barrier(0);     // bounds live address registers
       }
       // chase frames t = 32b+n .. 32b+1: one readlane of the state's code

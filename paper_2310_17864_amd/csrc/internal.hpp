@@ -134,26 +134,27 @@ struct ServeBox {                 // per resident workgroup b (host memory)
 };
 
 // Backpointer layout.  Frames 1..T-1 carry backpointers, in groups of 8
-// frames.  Per state slot a lane produces one "moved" bit (came from s-1 or
-// s-2) and, for label slots, one "skipped" bit (came from s-2).  A lane's
-// P = 3M/2 bit planes are numbered in the order the forward pass produces them
-// (slot pairs from the top down: moved(odd), skipped(odd), moved(even)) and
-// dealt round-robin over its NQ = ceil(P/4) words (plane p -> word p % NQ,
-// position p / NQ), so consecutive planes land in different words and their
-// shift-ins do not wait on each other.  Word q holds R_q planes interleaved by
-// frame: the plane at position r, frame i of the group sits at bit
-// 31 - (R_q*i + r).  Words are stored [segment][group][word][lane].
-__host__ __device__ constexpr int bp_planes(int M) { return 3 * M / 2; }
+// frames, one bit per state slot and frame.  A blank slot's bit says whether
+// it came from the state below.  A label slot's bit says whether it came from
+// below at all; which of the two states below it came from is then the bit
+// of the blank slot under it in the same frame (that blank already chose the
+// better of the same two states, ties to the nearer one), unless the label
+// may not skip (it repeats the previous label), in which case it came from
+// the state just below.  A lane's P = M bit planes are numbered in the order
+// the forward pass produces them (slot pairs from the top down: label, then
+// blank) and dealt round-robin over its NQ = ceil(P/4) words (plane p ->
+// word p % NQ, position p / NQ), so consecutive planes land in different
+// words and their shift-ins do not wait on each other.  Word q holds R_q
+// planes interleaved by frame: the plane at position r, frame i of the group
+// sits at bit 31 - (R_q*i + r).  Words are stored [segment][group][word][lane].
+__host__ __device__ constexpr int bp_planes(int M) { return M; }
 __host__ __device__ constexpr int bp_words_per_lane(int M) { return (bp_planes(M) + 3) / 4; }
 __host__ __device__ inline int64_t bp_groups(int64_t T) { return (T - 1 + kUnroll - 1) / kUnroll; }
 __host__ __device__ inline int64_t bp_words(int64_t T, int W, int M) {
   return (int64_t)W * bp_groups(T) * bp_words_per_lane(M) * kWave;
 }
-// plane index of slot j's "moved" bit and of a label slot's "skipped" bit
-__host__ __device__ constexpr int plane_mv(int M, int j) {
-  return (j % 2) ? 3 * (M / 2 - 1 - j / 2) : 3 * (M / 2 - 1 - j / 2) + 2;
-}
-__host__ __device__ constexpr int plane_sk(int M, int j) { return 3 * (M / 2 - 1 - j / 2) + 1; }
+// plane index of slot j's bit
+__host__ __device__ constexpr int plane_of(int M, int j) { return 2 * (M / 2 - 1 - j / 2) + ((j % 2) ? 0 : 1); }
 __host__ __device__ constexpr int planes_in_word(int M, int q) {
   return (bp_planes(M) - q + bp_words_per_lane(M) - 1) / bp_words_per_lane(M);
 }
