@@ -100,7 +100,8 @@ __device__ __forceinline__ bool wait_geq(int* p, int need) {
 //
 // a[j] holds a_{t-1} for state sbase+j on entry and a_t on exit.  Slot pairs
 // (blank 2p, label 2p+1) are updated from the top down so every read sees
-// a_{t-1}.  nb is a_{t-1} of the state just below this lane's first one.
+// a_{t-1}.  nb is a_{t-1} of the state just below this lane's first one (one
+// DPP shift of the lanes' top states, lane 0 keeping the boundary value).
 // With x = a(s), y = a(s-1), z = a(s-2) for label s, the strict rule picks
 // s-2 iff z > y and z > x, s-1 iff y >= z and y > x, else s; the blank s-1
 // has already compared z with y (its own s-1 and s), so the label compares
@@ -117,11 +118,8 @@ __device__ __forceinline__ float bitsel(uint32_t k, float x, float y) {
 
 template <int M>
 __device__ __forceinline__ void dp_frame(float (&a)[M], uint32_t (&acc)[bp_words_per_lane(M)],
-                                         const uint32_t (&kb)[M / 2], float nbs,
-                                         float nb_in, float eb, const float (&e)[M / 2]) {
-  // lane 0 takes the boundary value from below; selected only where the
-  // lowest pair uses it, so its LDS read may still be in flight until then
-  const float nb = sel(1ull, nb_in, nbs);
+                                         const uint32_t (&kb)[M / 2], float nb, float eb,
+                                         const float (&e)[M / 2]) {
 #pragma unroll
   for (int p = M / 2 - 1; p >= 0; --p) {
     const int jb = 2 * p, jl = 2 * p + 1;
@@ -171,27 +169,33 @@ struct Ring {
 
 __device__ __forceinline__ float* ring_quarter(const Ring& r, int q) { return r.base + q * 2 * kMaxC; }
 
-// One 16-byte-per-lane copy of global memory into LDS at lds_dst + 16*lane.
+// One 16-byte-per-lane copy of global memory into LDS at lds_dst + 16*lane:
+// lane l reads row + lane_off[l] (row in scalar registers, the per-lane byte
+// offset in a vector register, so the address costs no vector instruction).
 // M0 holds the LDS address; one wait state separates its write from the copy.
-__device__ __forceinline__ void dma_row(const float* src, float* lds_dst) {
+__device__ __forceinline__ void dma_row(const float* row, uint32_t lane_off, float* lds_dst) {
   const uint32_t l = (uint32_t)(uintptr_t)(lds_void_t*)lds_dst;
   asm volatile(
       "s_mov_b32 m0, %0\n\t"
       "s_nop 0\n\t"
-      "global_load_lds_dwordx4 %1, off" ::"s"(l),
-      "v"(src)
+      "global_load_lds_dwordx4 %1, %2" ::"s"(l),
+      "v"(lane_off), "s"(row)
       : "memory", "m0");
 }
 
-__device__ __forceinline__ void dma_chunk(const float* em, int T, int hs, int k, int lane, float* quarter) {
+// 1 KB rows: 64 lanes x 16 bytes; 128-byte rows: lanes 0..7 carry the data,
+// the others repeat it into the unused part of the LDS row.
+__device__ __forceinline__ uint32_t dma_lane_off(int hs, int lane) {
+  return 16u * (uint32_t)(hs == kMaxC ? lane : (lane & 7));
+}
+
+__device__ __forceinline__ void dma_chunk(const float* em, int T, int hs, int k, uint32_t lane_off,
+                                          float* quarter) {
 #pragma unroll
   for (int r = 0; r < kDmaPerChunk; ++r) {
     int row = 2 * k + 1 + r;
     row = row < T ? row : T - 1;                     // clamped: always issued
-    const float* src = em + (int64_t)row * hs;
-    // 1 KB rows: 64 lanes x 16 bytes; 128-byte rows: lanes 0..7 carry the
-    // data, the others repeat it into the unused part of the LDS row
-    dma_row(src + 4 * (hs == kMaxC ? lane : (lane & 7)), quarter + r * kMaxC);
+    dma_row(em + (int64_t)row * hs, lane_off, quarter + r * kMaxC);
   }
 }
 
@@ -351,9 +355,17 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   SegSync* me = sy + wl;
   SegSync* prev = has_prev ? (prev_x ? xl.in_lds : sy + wl - 1) : nullptr;
   SegSync* next = (has_next && !next_x) ? sy + wl + 1 : nullptr;
-  // boundary values are read every frame through a pointer that always points
-  // into the SegSync array (the compiler then knows it cannot alias the ring)
-  const SegSync* pv = has_prev ? prev : me;
+  // Boundary values are read every frame through a pointer that always points
+  // into the SegSync array (the compiler then knows it cannot alias the ring).
+  // The lowest segment reads -inf (the state below state 0) from a ring no
+  // other segment of the instance uses: the top segment's own (a top segment
+  // never publishes) or, in the multi layout, the first workgroup's copy of
+  // incoming values (it has none).
+  SegSync* pv = prev;
+  if (!has_prev) {
+    pv = kX ? xl.in_lds : sy + (W - 1);
+    for (int k = lane; k < kBnd; k += kWave) pv->bnd[k] = neg_inf();
+  }
   int x_seen = 0;                         // consumer progress seen by a cross-workgroup producer
   if (has_next) {
     if (lane == kWave - 1) me->bnd[0] = a[M - 1];
@@ -370,6 +382,7 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   uint32_t* bpw = in.bp + (int64_t)w * ngrp * NQ * kWave + lane;
 
   const int hs = in.stride;
+  const uint32_t dma_off = dma_lane_off(hs, lane);
   // Small lanes read each frame's emissions one frame ahead (M/2+1 more
   // registers), hiding the LDS latency behind the previous frame's work.
   constexpr bool kAhead = M <= 16;
@@ -377,11 +390,11 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
 #pragma unroll
   for (int jj = 0; jj < M / 2; ++jj) e_c[jj] = 0.f;
   if (nsteps > 0) {
-    dma_chunk(em, T, hs, 0, lane, ring_quarter(ring, 0));
-    dma_chunk(em, T, hs, 1, lane, ring_quarter(ring, 1));
-    dma_chunk(em, T, hs, 2, lane, ring_quarter(ring, 2));
+    dma_chunk(em, T, hs, 0, dma_off, ring_quarter(ring, 0));
+    dma_chunk(em, T, hs, 1, dma_off, ring_quarter(ring, 1));
+    dma_chunk(em, T, hs, 2, dma_off, ring_quarter(ring, 2));
     wait_vm_keep<kDmaAfter>();     // chunk 0 has landed
-    dma_chunk(em, T, hs, 3, lane, ring_quarter(ring, 3));
+    dma_chunk(em, T, hs, 3, dma_off, ring_quarter(ring, 3));
     if constexpr (kAhead) {
       const float* r0 = ring_quarter(ring, 0);
       eb_c = r0[blank];
@@ -449,11 +462,15 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
           const int k = (uu + 1) / 2;
           wait_vm_keep<kDmaAfter>();
           asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-          dma_chunk(em, T, hs, k + 3, lane, ring_quarter(ring, (i / 2) % 4));
+          dma_chunk(em, T, hs, k + 3, dma_off, ring_quarter(ring, (i / 2) % 4));
         }
-        // this frame's boundary value was read one frame ahead; read the
-        // next one first (LDS reads complete in order)
-        const float bv = bv_c;
+        // this frame's boundary value was read one frame ahead: lane 0 takes
+        // it, the other lanes their left neighbour's top state.  Done before
+        // the next frame's reads are issued (the compiler waits for every
+        // outstanding LDS read at this use), then the reads, then this frame's
+        // arithmetic, which hides their latency.
+        const float nb = shr1(a[M - 1], bv_c);
+        __builtin_amdgcn_sched_barrier(0);
         bv_c = pv->bnd[(uu + 1) % kBnd];
         float eb_n = 0.f, e_n[M / 2];
         if constexpr (kAhead) {
@@ -463,9 +480,8 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
 #pragma unroll
           for (int jj = 0; jj < M / 2; ++jj) e_n[jj] = rn[eoff[jj]];
         }
-        const float nb_in = has_prev ? bv : neg_inf();
-        const float nbs = shr1(a[M - 1], a[M - 1]);
-        dp_frame<M>(a, acc, skip, nbs, nb_in, eb_c, e_c);
+        __builtin_amdgcn_sched_barrier(0);
+        dp_frame<M>(a, acc, skip, nb, eb_c, e_c);
         if (has_next && lane == kWave - 1) me->bnd[(uu + 1) % kBnd] = a[M - 1];
         if constexpr (kAhead) {
           eb_c = eb_n;
@@ -501,10 +517,7 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
           float e[M / 2];
 #pragma unroll
           for (int jj = 0; jj < M / 2; ++jj) e[jj] = rc[eoff[jj]];
-          const float bv = pv->bnd[uu % kBnd];
-          const float nb_in = has_prev ? bv : neg_inf();
-          const float nbs = shr1(a[M - 1], a[M - 1]);
-          dp_frame<M>(a, acc, skip, nbs, nb_in, eb, e);
+          dp_frame<M>(a, acc, skip, shr1(a[M - 1], pv->bnd[uu % kBnd]), eb, e);
           if (has_next && lane == kWave - 1) me->bnd[(uu + 1) % kBnd] = a[M - 1];
           u = uu;
         }
@@ -609,10 +622,10 @@ __device__ __forceinline__ bool prologue_check(const Inst& in, int w, int lane) 
 // The chase s_{t-1} = s_t - k_t(s_t) runs in scalar registers, 32 frames per
 // block.  Over one block the state drops by at most 62, so the block's codes
 // for the 63 states at and below the block's top state sit one per lane (the
-// "band"), each as two 32-frame words with frame i of the block at bit 31-i:
-// the state's own bit and, for a label state that may skip, the bit of the
-// blank state below it (which of the two states below the label came from);
-// a frame then costs two readlanes.  Lane i records the state of the block's
+// "band"), as 2-bit codes built from each state's own 32 frame bits and, for
+// a label state that may skip, those of the blank state below it (the next
+// lane: which of the two states below the label it came from); a frame then
+// costs one readlane.  Lane i records the state of the block's
 // frame i; its label is fetched after the chase and stored one block later.
 //
 // Fetches run two blocks ahead: at the top of block b (state e_b) the raw
@@ -651,21 +664,19 @@ __device__ __forceinline__ Band make_band(uint32_t mv, uint32_t sk) {
   return Band{(spread16(sk >> 16) << 1) | spread16(lo >> 16), (spread16(sk) << 1) | spread16(lo)};
 }
 
-// Raw backpointer words of one state for the 4 groups of a block: the word
-// holding its own plane and the word holding the plane of the blank below it
-// (label states; blank states load their own word twice), plus the two labels
-// whose difference is a label state's skip permission (label 0 twice for
-// other states).
+// Raw backpointer words of one state for the 4 groups of a block (the word
+// holding its plane), plus the two labels whose difference is a label
+// state's skip permission (label 0 twice for other states).  The bit of the
+// blank below a label state is the next band lane's own bit.
 struct RawWin {
-  uint32_t wm[4], ws[4];
+  uint32_t wm[4];
   int32_t la, lb;
 };
 
-// Where state q's plane and its partner's sit in a lane's words.
+// Where state q's plane sits in a lane's words.
 struct PlaneLoc {
   int wseg, ln;          // segment, lane
-  int qm, pm, rm;        // own plane: word, bit offset, planes in the word
-  int qs, ps, rs;        // plane of the blank below (label slots; blank slots repeat their own)
+  int qm, pm, rm;        // word, bit offset, planes in the word
   bool odd;
 };
 
@@ -679,35 +690,29 @@ __device__ __forceinline__ PlaneLoc plane_loc(int q) {
   const int j = rr - p.ln * M;
   p.odd = j % 2;
   const int pown = plane_of(M, j);
-  const int pblk = p.odd ? plane_of(M, j - 1) : pown;   // the blank of the pair sits in the same lane
   p.qm = plane_word(M, pown);
   p.pm = plane_pos(M, pown);
   p.rm = planes_in_word(M, p.qm);
-  p.qs = plane_word(M, pblk);
-  p.ps = plane_pos(M, pblk);
-  p.rs = planes_in_word(M, p.qs);
   return p;
 }
 
+typedef __attribute__((address_space(1))) const uint32_t gu32_t;
+typedef __attribute__((address_space(1))) const int32_t gi32_t;
+
 // labp: the labels (any readable int32 array when there are none: only
-// state 0 then exists and reads index 0).
+// state 0 then exists and reads index 0).  Groups are read at fixed offsets
+// from the block's first (the layout holds whole blocks).
 template <int M>
 __device__ __forceinline__ RawWin load_win(const Inst& in, const int* labp, int blk, int ngrp, int q) {
   RawWin r;
   constexpr int NQ = bp_words_per_lane(M);
   const PlaneLoc p = plane_loc<M>(q > 0 ? q : 0);
-  const uint32_t* base = in.bp + ((int64_t)p.wseg * ngrp) * NQ * kWave + p.ln;
+  gu32_t* base = (gu32_t*)in.bp + ((int64_t)p.wseg * ngrp + 4 * blk) * NQ * kWave + p.qm * kWave + p.ln;
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    int gi = 4 * blk + g;
-    gi = gi < ngrp ? gi : ngrp - 1;               // past the last group: unused bits
-    const uint32_t* gb = base + (int64_t)gi * NQ * kWave;
-    r.wm[g] = gb[p.qm * kWave];
-    r.ws[g] = gb[p.qs * kWave];
-  }
+  for (int g = 0; g < 4; ++g) r.wm[g] = base[g * NQ * kWave];
   const bool lab2 = (q >= 3) && (q % 2);          // a label state with a label two below
-  r.la = labp[lab2 ? (q - 1) / 2 : 0];
-  r.lb = labp[lab2 ? (q - 3) / 2 : 0];
+  r.la = ((gi32_t*)labp)[lab2 ? (q - 1) / 2 : 0];
+  r.lb = ((gi32_t*)labp)[lab2 ? (q - 3) / 2 : 0];
   return r;
 }
 
@@ -729,13 +734,19 @@ __device__ __forceinline__ uint32_t bperm(uint32_t v, int src_lane) {
   return (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane * 4, (int)v);
 }
 
-// Band of state q from its own plane's and its blank partner's 32 frame bits
-// and the two labels fetched for it: a label state came from s-2 where it
-// came from below, may skip, and the blank below came from below too.
+// lane l receives src from lane l+1 (lane 63 keeps src).
+__device__ __forceinline__ uint32_t shl1(uint32_t src) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)src, (int)src, 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
+}
+
+// Band of state q (lane l of a band of consecutive states, q = top - l) from
+// its own 32 frame bits mv and the two labels fetched for it: a label state
+// came from s-2 where it came from below, may skip, and the blank below it
+// (the next lane) came from below too.
 template <int M>
-__device__ __forceinline__ Band band_from(uint32_t mv, uint32_t pb, int32_t la, int32_t lb, int q,
-                                          const PlaneLoc& p) {
+__device__ __forceinline__ Band band_from(uint32_t mv, int32_t la, int32_t lb, int q, const PlaneLoc& p) {
   if (q < 0) mv = 0u;
+  const uint32_t pb = shl1(mv);
   const bool may_skip = q >= 3 && p.odd && la != lb;
   const uint32_t sk = may_skip ? (mv & pb) : 0u;
   return make_band(mv, sk);
@@ -753,28 +764,22 @@ __device__ __forceinline__ Band band_of(const RawWin& a, const RawWin& b, const 
     return k == 0 ? ra : (k == 1 ? rb : rc);
   };
   const PlaneLoc p = plane_loc<M>(q > 0 ? q : 0);
-  uint32_t mv = 0u, pb = 0u;
+  uint32_t mv = 0u;
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    mv |= gather8(pick(a.wm[g], b.wm[g], c.wm[g]), p.rm, p.pm) >> (kUnroll * g);
-    pb |= gather8(pick(a.ws[g], b.ws[g], c.ws[g]), p.rs, p.ps) >> (kUnroll * g);
-  }
+  for (int g = 0; g < 4; ++g) mv |= gather8(pick(a.wm[g], b.wm[g], c.wm[g]), p.rm, p.pm) >> (kUnroll * g);
   // only whether the two labels differ matters
   const uint32_t dl = pick((uint32_t)(a.la ^ a.lb), (uint32_t)(b.la ^ b.lb), (uint32_t)(c.la ^ c.lb));
-  return band_from<M>(mv, pb, (int32_t)dl, 0, q, p);
+  return band_from<M>(mv, (int32_t)dl, 0, q, p);
 }
 
 // Band of state q straight from one window (no realignment).
 template <int M>
 __device__ __forceinline__ Band band_direct(const RawWin& a, int q) {
   const PlaneLoc p = plane_loc<M>(q > 0 ? q : 0);
-  uint32_t mv = 0u, pb = 0u;
+  uint32_t mv = 0u;
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    mv |= gather8(a.wm[g], p.rm, p.pm) >> (kUnroll * g);
-    pb |= gather8(a.ws[g], p.rs, p.ps) >> (kUnroll * g);
-  }
-  return band_from<M>(mv, pb, a.la, a.lb, q, p);
+  for (int g = 0; g < 4; ++g) mv |= gather8(a.wm[g], p.rm, p.pm) >> (kUnroll * g);
+  return band_from<M>(mv, a.la, a.lb, q, p);
 }
 
 // f(integral_constant<N-1>), ..., f(integral_constant<0>)

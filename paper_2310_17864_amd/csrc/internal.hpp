@@ -149,7 +149,12 @@ struct ServeBox {                 // per resident workgroup b (host memory)
 // sits at bit 31 - (R_q*i + r).  Words are stored [segment][group][word][lane].
 __host__ __device__ constexpr int bp_planes(int M) { return M; }
 __host__ __device__ constexpr int bp_words_per_lane(int M) { return (bp_planes(M) + 3) / 4; }
-__host__ __device__ inline int64_t bp_groups(int64_t T) { return (T - 1 + kUnroll - 1) / kUnroll; }
+// groups per segment, rounded up to whole 32-frame blocks (the backtrack
+// reads a block's four groups at fixed offsets; the tail is never used)
+__host__ __device__ inline int64_t bp_groups(int64_t T) {
+  constexpr int64_t per_blk = kBlk / kUnroll;
+  return (T - 1 + kBlk - 1) / kBlk * per_blk;
+}
 __host__ __device__ inline int64_t bp_words(int64_t T, int W, int M) {
   return (int64_t)W * bp_groups(T) * bp_words_per_lane(M) * kWave;
 }

@@ -150,7 +150,7 @@ def apply(ctx, kind: int, C: int, best: Dict[int, Tuple[int, int, float]]) -> Li
 
 
 KNOB_GRID = {
-    "pack_target_m": (8, 10, 12, 14, 16),
+    "pack_target_m": (6, 8, 10, 12, 14, 16),
     "crit_frac": (0.0, 0.4, 0.5, 0.6, 0.7, 0.8),
     "crit_per_cu": (0.5, 1.0, 1.5),
 }
