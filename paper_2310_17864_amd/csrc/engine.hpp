@@ -46,8 +46,24 @@ struct SegSync {
   int cons;          // previous segment's values consumed by this segment (count)
   int done;          // 1 once this segment's backpointers are stored
   int bad;           // 1 if this segment saw an invalid label
-  float bnd[kBnd];   // a_t(last state of this segment), slot t % kBnd
+  float bnd[kBnd + 1];   // a_t(last state of this segment) in slot bslot(t)
 };
+
+// Ring slot of frame t's boundary value: 0 for t = 0, then 1 + (t-1) mod kBnd,
+// so the 8 frames 8g+1 .. 8g+8 of a group sit in consecutive slots (fixed
+// offsets from the group's first).
+static_assert((kBnd & (kBnd - 1)) == 0 && kBnd % kUnroll == 0, "ring of whole groups");
+__device__ __forceinline__ int bslot(int t) { return t == 0 ? 0 : ((t - 1) & (kBnd - 1)) + 1; }
+
+typedef __attribute__((address_space(3))) float lds_f32;
+
+// An LDS address held in a vector register (the compiler would otherwise
+// copy it from a scalar register before every access).
+__device__ __forceinline__ lds_f32* vreg_lds(const float* p) {
+  uint32_t a = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void*)p;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(a) : "v"(a));
+  return (lds_f32*)(uintptr_t)a;
+}
 
 constexpr int kSpinLimit = 1 << 26;   // bounded waits: ~seconds, never forever
 
@@ -116,10 +132,14 @@ __device__ __forceinline__ float bitsel(uint32_t k, float x, float y) {
   return r;
 }
 
+// pub: lane 63 of a segment with a segment above (pub_seg, uniform) stores
+// a_t of its top state to *pub as soon as the top pair is done, so the LDS
+// write has the rest of the frame to complete.
 template <int M>
 __device__ __forceinline__ void dp_frame(float (&a)[M], uint32_t (&acc)[bp_words_per_lane(M)],
                                          const uint32_t (&kb)[M / 2], float nb, float eb,
-                                         const float (&e)[M / 2]) {
+                                         const float (&e)[M / 2], bool pub_seg, bool pub_lane,
+                                         lds_f32* pub) {
 #pragma unroll
   for (int p = M / 2 - 1; p >= 0; --p) {
     const int jb = 2 * p, jl = 2 * p + 1;
@@ -134,6 +154,9 @@ __device__ __forceinline__ void dp_frame(float (&a)[M], uint32_t (&acc)[bp_words
     acc[plane_word(M, plane_of(M, jb))] = shift_in(acc[plane_word(M, plane_of(M, jb))], cb);
     a[jl] = e[p] + wl;
     a[jb] = eb + wb;
+    if (p == M / 2 - 1 && pub_seg) {
+      if (pub_lane) *pub = a[M - 1];
+    }
   }
 }
 
@@ -195,7 +218,9 @@ __device__ __forceinline__ void dma_chunk(const float* em, int T, int hs, int k,
   for (int r = 0; r < kDmaPerChunk; ++r) {
     int row = 2 * k + 1 + r;
     row = row < T ? row : T - 1;                     // clamped: always issued
-    dma_row(em + (int64_t)row * hs, lane_off, quarter + r * kMaxC);
+    // strides are 32 or 256 floats: the byte offset is one 64-bit shift
+    const int sh = hs == kMaxC ? 10 : 7;
+    dma_row((const float*)((const char*)em + ((uint64_t)(uint32_t)row << sh)), lane_off, quarter + r * kMaxC);
   }
 }
 
@@ -245,7 +270,7 @@ __device__ __forceinline__ bool x_pull(XChan* ch, SegSync* dst, int i0, int cnt,
     if (lane < cnt) v = x_load(&ch->slot[i % kXRing]);
     const bool ok = lane >= cnt || (uint32_t)(v >> 32) == (tag | (uint32_t)i);
     if (__builtin_amdgcn_ballot_w64(!ok) == 0) {
-      if (lane < cnt) dst->bnd[i % kBnd] = __builtin_bit_cast(float, (uint32_t)v);
+      if (lane < cnt) dst->bnd[bslot(i)] = __builtin_bit_cast(float, (uint32_t)v);
       if (lane == 0)
         __hip_atomic_store(&ch->cons, (int32_t)(tag | (uint32_t)(i0 + cnt - 1)), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_SYSTEM);
@@ -273,7 +298,7 @@ __device__ __forceinline__ bool x_room(XChan* ch, int i_end, int& seen, uint32_t
 __device__ __forceinline__ void x_push(XChan* ch, const SegSync* src, int i0, int cnt, int lane, uint32_t tag) {
   if (lane < cnt) {
     const int i = i0 + lane;
-    const uint32_t bits = __builtin_bit_cast(uint32_t, src->bnd[i % kBnd]);
+    const uint32_t bits = __builtin_bit_cast(uint32_t, src->bnd[bslot(i)]);
     x_store(&ch->slot[i % kXRing], ((uint64_t)(tag | (uint32_t)i) << 32) | bits);
   }
 }
@@ -364,7 +389,7 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   SegSync* pv = prev;
   if (!has_prev) {
     pv = kX ? xl.in_lds : sy + (W - 1);
-    for (int k = lane; k < kBnd; k += kWave) pv->bnd[k] = neg_inf();
+    for (int k = lane; k <= kBnd; k += kWave) pv->bnd[k] = neg_inf();
   }
   int x_seen = 0;                         // consumer progress seen by a cross-workgroup producer
   if (has_next) {
@@ -406,6 +431,7 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   uint32_t acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0;
+  lds_f32* const ebp = vreg_lds(ring.base + blank);   // the blank column of ring row 0
 
   // neighbours in one workgroup hand over boundary values every 8-frame
   // group in the batched and single kernels, every 32-frame block in the
@@ -444,7 +470,10 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
           alive &= wait_geq(&next->cons, ubase + ne - kBnd + 1);
         if (!alive) break;
       }
-      if (g == 0) bv_c = pv->bnd[(32 * b) % kBnd];   // boundary value of the block's first frame
+      if (g == 0) bv_c = pv->bnd[bslot(32 * b)];   // boundary value of the block's first frame
+      // this group's boundary slots: frame ubase+i+1 at offset i
+      lds_f32* const grp_rd = vreg_lds(pv->bnd + bslot(ubase + 1));
+      lds_f32* const grp_wr = vreg_lds(me->bnd + bslot(ubase + 1));
       // One frame: i is the frame's static position in the group.
       auto frame = [&](auto ic) __attribute__((always_inline)) {
         constexpr int i = decltype(ic)::value;
@@ -471,18 +500,17 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
         // arithmetic, which hides their latency.
         const float nb = shr1(a[M - 1], bv_c);
         __builtin_amdgcn_sched_barrier(0);
-        bv_c = pv->bnd[(uu + 1) % kBnd];
+        bv_c = grp_rd[i];
         float eb_n = 0.f, e_n[M / 2];
         if constexpr (kAhead) {
           // the next frame's values, read while this frame computes
           const float* rn = ring_quarter(ring, ((i + 1) / 2) % 4) + ((i + 1) % 2) * kMaxC;
-          eb_n = rn[blank];
+          eb_n = ebp[(((i + 1) / 2) % 4) * 2 * kMaxC + ((i + 1) % 2) * kMaxC];
 #pragma unroll
           for (int jj = 0; jj < M / 2; ++jj) e_n[jj] = rn[eoff[jj]];
         }
         __builtin_amdgcn_sched_barrier(0);
-        dp_frame<M>(a, acc, skip, nb, eb_c, e_c);
-        if (has_next && lane == kWave - 1) me->bnd[(uu + 1) % kBnd] = a[M - 1];
+        dp_frame<M>(a, acc, skip, nb, eb_c, e_c, has_next, lane == kWave - 1, grp_wr + i);
         if constexpr (kAhead) {
           eb_c = eb_n;
 #pragma unroll
@@ -517,8 +545,8 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
           float e[M / 2];
 #pragma unroll
           for (int jj = 0; jj < M / 2; ++jj) e[jj] = rc[eoff[jj]];
-          dp_frame<M>(a, acc, skip, shr1(a[M - 1], pv->bnd[uu % kBnd]), eb, e);
-          if (has_next && lane == kWave - 1) me->bnd[(uu + 1) % kBnd] = a[M - 1];
+          dp_frame<M>(a, acc, skip, shr1(a[M - 1], pv->bnd[bslot(uu)]), eb, e, has_next,
+                      lane == kWave - 1, grp_wr + i);
           u = uu;
         }
       }
@@ -582,7 +610,7 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
       // a_0(S-2) = -inf since S-2 >= 2)
       float f2 = neg_inf();
       if (prev_x) out.ok = 0;   // not a layout of the multi-workgroup kernel
-      else if (in.T > 1) f2 = pv->bnd[(in.T - 1) % kBnd];
+      else if (in.T > 1) f2 = pv->bnd[bslot(in.T - 1)];
       const bool take2 = f2 > f1;
       out.total = take2 ? f2 : f1;
       out.send = take2 ? S - 2 : S - 1;
@@ -782,6 +810,23 @@ __device__ __forceinline__ Band band_direct(const RawWin& a, int q) {
   return band_from<M>(mv, a.la, a.lb, q, p);
 }
 
+// Two frames per lookup.  In a band word, frame pair j (frames 2j+1, 2j)
+// is the nibble at bits 31-4j .. 28-4j: frame 2j+1's code below, frame 2j's
+// above.  The chase meets frame 2j+1 first, at the lane's own state, and
+// frame 2j at the state k1 = code(2j+1) lanes further; so the upper half of
+// each nibble is replaced by that lane's code (k1 <= 2: the lane itself, its
+// next or the one after, moved by two DPP shifts).  One readlane then yields
+// both drops.  Lanes 62 and 63 receive garbage from beyond the band; a chase
+// never reaches them before the block's last pair is read.
+__device__ __forceinline__ uint32_t pair_codes(uint32_t w) {
+  const uint32_t n1 = shl1(w), n2 = shl1(n1);
+  const uint32_t lo1 = w & 0x11111111u;          // k1 == 1
+  const uint32_t lo2 = (w >> 1) & 0x11111111u;   // k1 == 2
+  const uint32_t m1 = lo1 * 12u, m2 = lo2 * 12u; // the nibble's upper two bits
+  const uint32_t t = (m1 & n1) | (~m1 & w);
+  return (m2 & n2) | (~m2 & t);
+}
+
 // f(integral_constant<N-1>), ..., f(integral_constant<0>)
 template <int N, typename F>
 __device__ __forceinline__ void unroll_down(F&& f) {
@@ -866,14 +911,20 @@ __device__ __forceinline__ void backtrack(const Inst& in, const FwdOut& fo, int 
         e -= (int)((w >> ((i < 16 ? 30 : 62) - 2 * i)) & 3u);
       };
       if (n == kBlk) {
-        // whole block: frame i's state goes to lane i by v_writelane with an
-        // immediate lane index (no per-frame lane mask)
-        auto chase_c = [&](auto ic) __attribute__((always_inline)) {
-          constexpr int i = decltype(ic)::value;
-          asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(outst) : "s"(__builtin_amdgcn_readfirstlane(e)), "n"(i));
-          step_code(i);
+        // whole block, two frames per readlane (pair_codes); frame i's state
+        // goes to lane i by v_writelane with an immediate lane index (no
+        // per-frame lane mask)
+        const uint32_t w0 = pair_codes(cur.c0), w1 = pair_codes(cur.c1);
+        auto chase_p = [&](auto jc) __attribute__((always_inline)) {
+          constexpr int j = decltype(jc)::value;   // frames 2j+1, 2j
+          constexpr int sh = 28 - 4 * (j & 7);
+          asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(outst) : "s"(__builtin_amdgcn_readfirstlane(e)), "n"(2 * j + 1));
+          const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)(j >= 8 ? w1 : w0), top - e);
+          const int e1 = e - (int)((w >> sh) & 3u);
+          asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(outst) : "s"(__builtin_amdgcn_readfirstlane(e1)), "n"(2 * j));
+          e = e1 - (int)((w >> (sh + 2)) & 3u);
         };
-        unroll_down<kBlk>(chase_c);
+        unroll_down<kBlk / 2>(chase_p);
       } else {
         for (int i = n - 1; i >= 0; --i) {
           outst = (lane == i) ? e : outst;
