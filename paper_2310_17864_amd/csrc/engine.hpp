@@ -192,35 +192,43 @@ struct Ring {
 
 __device__ __forceinline__ float* ring_quarter(const Ring& r, int q) { return r.base + q * 2 * kMaxC; }
 
-// One 16-byte-per-lane copy of global memory into LDS at lds_dst + 16*lane:
-// lane l reads row + lane_off[l] (row in scalar registers, the per-lane byte
-// offset in a vector register, so the address costs no vector instruction).
-// M0 holds the LDS address; one wait state separates its write from the copy.
-__device__ __forceinline__ void dma_row(const float* row, uint32_t lane_off, float* lds_dst) {
+// One 16-byte-per-lane copy of global memory into LDS at lds_dst + 16*lane
+// by the lanes in `mask`: lane l reads row + lane_off[l] (row in scalar
+// registers, the per-lane byte offset in a vector register, so the address
+// costs no vector instruction).  M0 holds the LDS address; one wait state
+// separates its write from the copy; EXEC is restored before the block ends.
+__device__ __forceinline__ void dma_row(const float* row, uint32_t lane_off, float* lds_dst, uint64_t mask) {
   const uint32_t l = (uint32_t)(uintptr_t)(lds_void_t*)lds_dst;
+  uint64_t saved;
   asm volatile(
-      "s_mov_b32 m0, %0\n\t"
+      "s_mov_b64 %0, exec\n\t"
+      "s_mov_b64 exec, %4\n\t"
+      "s_mov_b32 m0, %1\n\t"
       "s_nop 0\n\t"
-      "global_load_lds_dwordx4 %1, %2" ::"s"(l),
-      "v"(lane_off), "s"(row)
+      "global_load_lds_dwordx4 %2, %3\n\t"
+      "s_mov_b64 exec, %0"
+      : "=&s"(saved)
+      : "s"(l), "v"(lane_off), "s"(row), "s"(mask)
       : "memory", "m0");
 }
 
-// 1 KB rows: 64 lanes x 16 bytes; 128-byte rows: lanes 0..7 carry the data,
-// the others repeat it into the unused part of the LDS row.
-__device__ __forceinline__ uint32_t dma_lane_off(int hs, int lane) {
-  return 16u * (uint32_t)(hs == kMaxC ? lane : (lane & 7));
-}
+// 1 KB rows: 64 lanes x 16 bytes.  128-byte rows: lanes 0..7 (the others
+// would only write copies into the unused part of the LDS row: 7/8 of the
+// row copy's LDS bandwidth).
+__device__ __forceinline__ uint32_t dma_lane_off(int lane) { return 16u * (uint32_t)lane; }
+__device__ __forceinline__ uint64_t dma_mask(int hs) { return hs == kMaxC ? ~0ull : 0xFFull; }
 
 __device__ __forceinline__ void dma_chunk(const float* em, int T, int hs, int k, uint32_t lane_off,
                                           float* quarter) {
+  const uint64_t mask = dma_mask(hs);
 #pragma unroll
   for (int r = 0; r < kDmaPerChunk; ++r) {
     int row = 2 * k + 1 + r;
     row = row < T ? row : T - 1;                     // clamped: always issued
     // strides are 32 or 256 floats: the byte offset is one 64-bit shift
     const int sh = hs == kMaxC ? 10 : 7;
-    dma_row((const float*)((const char*)em + ((uint64_t)(uint32_t)row << sh)), lane_off, quarter + r * kMaxC);
+    dma_row((const float*)((const char*)em + ((uint64_t)(uint32_t)row << sh)), lane_off, quarter + r * kMaxC,
+            mask);
   }
 }
 
@@ -407,7 +415,7 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
   uint32_t* bpw = in.bp + (int64_t)w * ngrp * NQ * kWave + lane;
 
   const int hs = in.stride;
-  const uint32_t dma_off = dma_lane_off(hs, lane);
+  const uint32_t dma_off = dma_lane_off(lane);
   // Small lanes read each frame's emissions one frame ahead (M/2+1 more
   // registers), hiding the LDS latency behind the previous frame's work.
   constexpr bool kAhead = M <= 16;
