@@ -173,26 +173,43 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persistent_batched4096_traffic.
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_persistent_batched4096_counters.txt")
 
 
+def _kv(path):
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    return kv
+
+
 def measured_issue():
     """VALU instructions of one replay (both batched kernels) from the
     committed counter summary, and the time they take at one wave64
-    instruction per 4 cycles on every SIMD (256 CUs x 4 SIMDs at 2.4 GHz);
-    None when the summary is missing or was taken on other sources."""
+    instruction per 4 cycles on every SIMD (256 CUs x 4 SIMDs) at the shader
+    clock measured in the same kernels (GRBM_GUI_ACTIVE over the dispatch
+    time; the 2.4 GHz peak clock when that summary is missing); None when the
+    counter summary is missing or was taken on other sources."""
     try:
-        kv = {}
-        with open(COUNTERS_FILE) as fh:
-            for line in fh:
-                if "=" in line and not line.startswith("#"):
-                    k, v = line.split("=", 1)
-                    kv[k.strip()] = v.strip()
+        kv = _kv(COUNTERS_FILE)
         if kv.get("kernel_source_hash") != kernel_source_hash():
             return None
         insts = sum(float(v) for k, v in kv.items() if k.endswith(" SQ_INSTS_VALU"))
-        return {"valu_wave_insts_per_replay": insts,
-                "issue_bound_ms": insts * 4 / (CU * SIMD * CLOCK) * 1e3}
+        clock, src = CLOCK, "peak"
+        try:
+            cv = _kv(VALUBUSY_FILE)
+            if cv.get("kernel_source_hash") == kernel_source_hash():
+                ghz = [float(v) for k, v in cv.items() if k.endswith(" clock_ghz")]
+                if ghz:
+                    clock, src = min(ghz) * 1e9, "measured"
+        except (OSError, ValueError):
+            pass
+        return {"valu_wave_insts_per_replay": insts, "clock_ghz": clock / 1e9, "clock": src,
+                "issue_bound_ms": insts * 4 / (CU * SIMD * clock) * 1e3}
     except (OSError, ValueError):
         return None
 TRAFFIC_LONG_FILE = os.path.join(ROOT, "profiles", "k_multi_long90000_traffic.txt")
+VALUBUSY_FILE = os.path.join(ROOT, "profiles", "k_persistent_batched4096_valubusy.txt")
 
 
 def kernel_source_hash():

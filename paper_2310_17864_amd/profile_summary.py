@@ -14,7 +14,8 @@ bench measured itself with HIP events in that same run.
 `counters` reads the counter_collection.csv of a `--pmc` run and records,
 per kernel, the median per-dispatch value of every counter collected, plus
 the ratios the kernel notes use (VALU instructions per active VALU cycle,
-wait share of wave cycles, LDS bank conflicts per LDS instruction).
+wait share of wave cycles, LDS bank conflicts per LDS instruction) and, when
+GRBM_GUI_ACTIVE was collected, the shader clock it implies.
 `traffic` reads the counter_collection.csv of two `--pmc FETCH_SIZE` /
 `--pmc WRITE_SIZE` runs, takes the median per-dispatch value of the
 persistent alignment kernel and of the calibration copy kernel (an
@@ -122,9 +123,13 @@ def traffic(fetch_dir: str, write_dir: str, out: str, copy_bytes: int, command: 
     print("\n".join(lines))
 
 
+XCDS = 8   # accelerator complex dies of an MI355X: GRBM_GUI_ACTIVE counts on each
+
+
 def counters(d: str, out: str, command: str, kernel: str = "ctca::") -> None:
     path = _find(d, "counter_collection.csv")
     per = {}      # (kernel, counter) -> {dispatch: value}
+    dur = {}      # (kernel, dispatch) -> seconds
     for r in csv.DictReader(open(path)):
         if kernel not in r["Kernel_Name"]:
             continue
@@ -132,6 +137,8 @@ def counters(d: str, out: str, command: str, kernel: str = "ctca::") -> None:
         key = (k, r["Counter_Name"])
         disp = per.setdefault(key, {})
         disp[r["Dispatch_Id"]] = disp.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+        if r.get("Start_Timestamp") and r.get("End_Timestamp"):
+            dur[(k, r["Dispatch_Id"])] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
     if not per:
         raise SystemExit(f"no counter rows for kernels matching {kernel!r} in {path}")
     lines = ["# rocprofv3 --pmc summary: per-dispatch medians per kernel",
@@ -151,6 +158,16 @@ def counters(d: str, out: str, command: str, kernel: str = "ctca::") -> None:
         ratio("SQ_WAIT_ANY", "SQ_WAVE_CYCLES", "wait_share_of_wave_cycles")
         ratio("SQ_LDS_BANK_CONFLICT", "SQ_INSTS_LDS", "lds_conflict_cycles_per_lds_inst")
         ratio("SQ_INSTS_VALU", "SQ_WAVES", "valu_insts_per_wave")
+        if (k, "GRBM_GUI_ACTIVE") in per:
+            # busy GPU cycles per dispatch over its duration: the shader clock
+            # (counted on every XCD), and the dispatch's duration under the
+            # counter collection (which runs dispatches one at a time)
+            g = per[(k, "GRBM_GUI_ACTIVE")]
+            clk = [v / dur[(k, i)] / XCDS for i, v in g.items() if dur.get((k, i), 0) > 0]
+            if clk:
+                lines.append(f"{k} clock_ghz = {statistics.median(clk) / 1e9:.4f}")
+                lines.append(f"{k} dispatch_ms_alone = "
+                             f"{statistics.median(dur[(k, i)] for i in g if (k, i) in dur) * 1e3:.4f}")
     open(out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
