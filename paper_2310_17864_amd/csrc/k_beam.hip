@@ -23,7 +23,7 @@
 // every score, every ranking decision and every label equals a plain
 // float32 evaluation in the same order bit for bit.
 //
-// Layout: one 256-thread workgroup per utterance; the beam (up to 16
+// Layout: one 256-thread workgroup per utterance, longest first; the beam (up to 16
 // hypotheses) and the frame's row (up to 1024 classes) in LDS.  A
 // hypothesis's labels live in a tree of nodes in global memory (one node per
 // extension, (parent node, label)); prefixes are compared by length and a
@@ -39,6 +39,7 @@
 // all candidates.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "ctx.hpp"
@@ -59,7 +60,7 @@ struct BeamDesc {
   int32_t* tok;          // B rows of T labels
   int2* nodes;           // T * B nodes: (parent node or -1, label)
   int32_t T;
-  int32_t pad_;
+  int32_t u;             // the utterance's index in the call (its output slots)
 };
 
 struct Hyp {
@@ -102,6 +103,13 @@ __device__ __forceinline__ uint64_t wave_max(uint64_t v) {
     v = u > v ? u : v;
   }
   return v;
+}
+
+// v of lane q, broadcast (two v_readlane: no LDS round trip)
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int q) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, q);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), q);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // h_j's prefix without its last label equals h_i's prefix (exact)
@@ -164,8 +172,8 @@ __global__ void __launch_bounds__(kBT) k_beam(const BeamDesc* __restrict__ descs
                                               int32_t* __restrict__ out_status) {
   __shared__ Shared sh;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int u = blockIdx.x;
-  const BeamDesc d = descs[u];
+  const BeamDesc d = descs[blockIdx.x];
+  const int u = d.u;
   const int T = d.T;
   if (tid == 0) {
     Hyp h{};
@@ -249,9 +257,19 @@ __global__ void __launch_bounds__(kBT) k_beam(const BeamDesc* __restrict__ descs
       }
       for (int w = tid; w < n * words; w += kBT) sh.merged[w / words][w % words] = 0u;
       if (tid < n) {
+        // the first i whose prefix is h_j's without its last label: length
+        // and hash read for every i at once, nodes compared, and only on a
+        // node mismatch the exact walk (parent_is)
+        const Hyp hj = sh.hyp[tid];
         int p = -1;
-        for (int i = 0; i < n && p < 0; ++i)
-          if (parent_is(sh.hyp[tid], sh.hyp[i], d.nodes)) p = i;
+#pragma unroll
+        for (int i = 0; i < kBMaxB; ++i) {
+          const int len_i = sh.hyp[i].len, node_i = sh.hyp[i].node;
+          const uint64_t hash_i = sh.hyp[i].hash;
+          if (p < 0 && i < n && hj.len == len_i + 1 && hj.phash == hash_i &&
+              (hj.pnode == node_i || parent_is(hj, sh.hyp[i], d.nodes)))
+            p = i;
+        }
         sh.child_of[tid] = p;
       }
       if (tid == 0) sh.cnt = 0;
@@ -273,7 +291,11 @@ __global__ void __launch_bounds__(kBT) k_beam(const BeamDesc* __restrict__ descs
         if (rm != 0ull) {
           const int cs = (int)(0xFFFFFFFFu - (uint32_t)rm);
           bool joins = false;
-          for (int k = 0; k < n; ++k) joins |= sh.child_of[k] == tid && sh.hyp[k].last == cs;
+#pragma unroll
+          for (int k = 0; k < kBMaxB; ++k) {
+            const int ck = sh.child_of[k], lk = sh.hyp[k].last;
+            joins |= k < n && ck == tid && lk == cs;
+          }
           if (!joins) {
             const Hyp& h = sh.hyp[tid];
             ek = make_key(0.0f + (cs == h.last ? h.pb : h.s) * sh.row[cs], tid * V + cs);
@@ -289,12 +311,12 @@ __global__ void __launch_bounds__(kBT) k_beam(const BeamDesc* __restrict__ descs
         uint64_t key = 0ull;
         if (lane < n) key = sh.stay_key[lane];
         else if (lane < 2 * n) key = sh.ext_key[lane - n];
-        int rank = 0, valid = 0;
-        for (int q = 0; q < 2 * n; ++q) {
-          const uint64_t o = q < n ? sh.stay_key[q] : sh.ext_key[q - n];
-          rank += o > key ? 1 : 0;
-          valid += o != 0ull ? 1 : 0;
-        }
+        // the keys are read once (lane q holds key q) and broadcast by
+        // readlane; every lane ranks its own
+        int rank = 0;
+#pragma unroll
+        for (int q = 0; q < 2 * kBMaxB; ++q) rank += (q < 2 * n && lane_u64(key, q) > key) ? 1 : 0;
+        const int valid = __builtin_popcountll(__builtin_amdgcn_ballot_w64(key != 0ull));
         if (lane == 0 && valid < B) sh.bound = 1ull;
         if (lane < 2 * n && key != 0ull && rank == B - 1 && valid >= B) sh.bound = key;
       }
@@ -523,14 +545,20 @@ int ctcalign_beam_decode(ctcalign_ctx* ctx, int32_t N, const float* probs, const
     if (rc) return rc;
     ws = static_cast<char*>(ctx->ws.ptr);
   }
+  // workgroups in order of decreasing frame count: the longest serial
+  // chains start first and the short ones fill in beside them
+  std::vector<int> order(N);
+  for (int i = 0; i < N; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return T[a] > T[b]; });
   std::vector<BeamDesc> descs(N);
   int2* nodes = reinterpret_cast<int2*>(ws + p.node_off);
-  for (int i = 0; i < N; ++i) {
-    descs[i].y = probs + prob_off[i];
-    descs[i].tok = out_tokens + tok_off[i];
-    descs[i].nodes = nodes + p.node_of[i];
-    descs[i].T = T[i];
-    descs[i].pad_ = 0;
+  for (int k = 0; k < N; ++k) {
+    const int i = order[k];
+    descs[k].y = probs + prob_off[i];
+    descs[k].tok = out_tokens + tok_off[i];
+    descs[k].nodes = nodes + p.node_of[i];
+    descs[k].T = T[i];
+    descs[k].u = i;
   }
   BeamDesc* d_desc = reinterpret_cast<BeamDesc*>(ws);
   HIP_TRY(hipMemcpyAsync(d_desc, descs.data(), sizeof(BeamDesc) * N, hipMemcpyHostToDevice, st));
