@@ -91,8 +91,10 @@ int ctcalign_ctx_destroy(ctcalign_ctx *ctx);
 /* Bytes of backpointer workspace one alignment of shape (T, L, C) needs under
  * the geometry this context would pick; 0 on invalid shape.  The backtrack of
  * the Viterbi recursion (paper Sec. 4, "CTC-based forced alignment") needs
- * the choice made at every state and frame: 1.5 bits per state and frame
- * here, laid out per wavefront, so the size depends on the geometry (W, M)
+ * the choice made at every state and frame: one bit per state and frame
+ * here (a label state's choice between the two states below it is the bit of
+ * the blank state under it), laid out per wavefront in whole 32-frame blocks,
+ * so the size depends on the geometry (W, M)
  * and therefore on the context's tuning table and on C, not on (T, L) alone.
  * Query again after ctcalign_tune_set / _load. */
 size_t ctcalign_workspace_bytes(ctcalign_ctx *ctx, int32_t T, int32_t L, int32_t C);

@@ -693,8 +693,8 @@ __device__ __forceinline__ uint32_t spread16(uint32_t x) {
   return x;
 }
 
-// codes from the moved / skipped words (frame i at bit 31-i): k = 2 if
-// skipped, else the moved bit
+// codes from the "came from below" and "came from two below" words (frame i
+// at bit 31-i): k = 2 where the second is set, else the first bit
 __device__ __forceinline__ Band make_band(uint32_t mv, uint32_t sk) {
   const uint32_t lo = mv & ~sk;
   return Band{(spread16(sk >> 16) << 1) | spread16(lo >> 16), (spread16(sk) << 1) | spread16(lo)};
