@@ -474,8 +474,8 @@ __device__ __forceinline__ FwdOut segment_forward(const Inst& in, const int w, c
       // still in the L2 the lower segment brought them into
       if constexpr (kGroupFlow) {
         if (has_prev && !prev_x) alive &= wait_geq(&prev->prod, ubase + ne + 1);
-        if (has_next && !next_x && ubase + ne - kBnd + 1 > 0)
-          alive &= wait_geq(&next->cons, ubase + ne - kBnd + 1);
+        if (has_next && !next_x && ubase + ne - kFlowWin + 1 > 0)
+          alive &= wait_geq(&next->cons, ubase + ne - kFlowWin + 1);
         if (!alive) break;
       }
       if (g == 0) bv_c = pv->bnd[bslot(32 * b)];   // boundary value of the block's first frame

@@ -9,6 +9,8 @@ constexpr int kBlk = 32;        // frames per backpointer word
 constexpr int kUnroll = 8;      // frames per unrolled group in the forward loop
 constexpr int kRing = 8;        // emission rows held in a wave's LDS ring (4 quarters x 2 rows)
 constexpr int kBnd = 128;       // boundary values held between two segments
+constexpr int kFlowWin = 32;    // frames a segment may run ahead of the one above it
+                                // (same workgroup, flow control per 8-frame group)
 constexpr int kMaxC = 256;      // largest class count served by the LDS ring
 constexpr int kPackWaves = 4;   // waves per workgroup in the persistent kernels
 
