@@ -65,9 +65,10 @@ def stats(d: str, out: str, command: str, top: int = 12, bench_json: str = "") -
             if line.startswith("{"):
                 rec = json.loads(line)
         if rec and "ms_per_step" in rec:
+            spread = (f" (min {rec['ms_min']:.4f}, max {rec['ms_max']:.4f})"
+                      if "ms_min" in rec and "ms_max" in rec else "")
             lines.append(f"# the same run's own step time (HIP events around each graph replay, "
-                         f"{rec.get('steps')} steps): ms_per_step = {rec['ms_per_step']:.4f} "
-                         f"(min {rec.get('ms_min', 0):.4f}, max {rec.get('ms_max', 0):.4f})")
+                         f"{rec.get('steps')} steps): ms_per_step = {rec['ms_per_step']:.4f}{spread}")
     lines.append(f"{'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_%':>8}  kernel")
     for r in rows[:top]:
         lines.append(f"{int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
