@@ -23,8 +23,11 @@
 // every score, every ranking decision and every label equals a plain
 // float32 evaluation in the same order bit for bit.
 //
-// Layout: one 256-thread workgroup per utterance, longest first; the beam (up to 16
-// hypotheses) and the frame's row (up to 1024 classes) in LDS.  A
+// Layout: one wavefront (a 64-thread workgroup) per utterance, longest
+// first, so a frame's steps need no workgroup barrier: lanes exchange values
+// by ballot, readlane and wave reductions, and LDS accesses of one wave are
+// ordered.  The beam (up to 16 hypotheses) and the frame's row (up to 1024
+// classes, 16 per lane) in LDS.  A
 // hypothesis's labels live in a tree of nodes in global memory (one node per
 // extension, (parent node, label)); prefixes are compared by length and a
 // 64-bit hash, confirmed by the node identity or, if the nodes differ, a
@@ -32,11 +35,12 @@
 //
 // Selection per frame: any B distinct candidates bound the B-th best key
 // from below; the bound is the B-th best among the stays and each
-// hypothesis's extension by the frame's most probable class.  Only
-// candidates at or above it enter an LDS list; the top B are ranked by
-// counting (a short list) or by repeated maximum (a long one); if the list
-// overflows, the whole workgroup picks the top B by repeated maximum over
-// all candidates.
+// hypothesis's extension by the frame's most probable class.  Only the
+// classes whose probability times the beam's largest factor reaches the
+// bound are paired with the hypotheses, and only candidates at or above the
+// bound enter an LDS list; the top B are ranked by counting (up to 64) or by
+// repeated maximum (a longer list); if the list overflows, the top B are
+// picked by repeated maximum over all candidates.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,10 +53,9 @@
 namespace ctca {
 namespace {
 
-constexpr int kBT = 256;          // threads per workgroup
+constexpr int kBT = 64;           // threads per workgroup: one wavefront per utterance
 constexpr int kBMaxB = 16;        // beam width limit
 constexpr int kBMaxV = 1024;      // class count limit
-constexpr int kBCols = kBMaxV / kBT;
 constexpr int kBList = 1024;      // candidates above the bound kept in LDS
 
 struct BeamDesc {
@@ -96,32 +99,41 @@ __device__ __forceinline__ uint64_t make_key(float tot, int idx) {
 }
 __device__ __forceinline__ int key_index(uint64_t k) { return (int)(0xFFFFFFFFu - (uint32_t)k); }
 
-__device__ __forceinline__ uint64_t wave_max(uint64_t v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const uint64_t u = __shfl_xor(v, o, 64);
-    v = u > v ? u : v;
-  }
-  return v;
+// Wavefront-wide operations (all 64 lanes active).  The reductions are the
+// ROCm device library's (DPP within rows, then across them).
+extern "C" __device__ __attribute__((const)) float __ockl_wfred_max_f32(float);
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_max_u64(unsigned long long);
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+// set bits of m below this lane
+__device__ __forceinline__ int below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
-
-// v of lane q, broadcast (two v_readlane: no LDS round trip)
+__device__ __forceinline__ uint64_t wave_max(uint64_t v) { return __ockl_wfred_max_u64(v); }
+// v of lane q (uniform q), broadcast by two v_readlane
 __device__ __forceinline__ uint64_t lane_u64(uint64_t v, int q) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, q);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), q);
   return ((uint64_t)hi << 32) | lo;
 }
 
-// h_j's prefix without its last label equals h_i's prefix (exact)
-__device__ bool parent_is(const Hyp& j, const Hyp& i, const int2* nodes) {
-  if (j.len != i.len + 1 || j.phash != i.hash) return false;
-  int a = j.pnode, b = i.node;
+// Global-memory views (plain global loads and stores: their completion is
+// not tied to the LDS counter the frame's steps wait on).
+typedef __attribute__((address_space(1))) const float gf32_t;
+typedef __attribute__((address_space(1))) const uint64_t gcu64_t;   // a node (int2) as one word
+typedef __attribute__((address_space(1))) uint64_t gu64_t;
+typedef __attribute__((address_space(1))) int32_t gi32_t;
+__device__ __forceinline__ int node_parent(uint64_t nd) { return (int)(uint32_t)nd; }
+__device__ __forceinline__ int node_label(uint64_t nd) { return (int)(uint32_t)(nd >> 32); }
+
+// Two node chains spell the same labels (exact; the caller has matched the
+// lengths and hashes)
+__device__ __noinline__ bool same_chain(int a, int b, gcu64_t* nodes) {
   while (a != b) {
     if (a < 0 || b < 0) return false;
-    const int2 na = nodes[a], nb = nodes[b];
-    if (na.y != nb.y) return false;
-    a = na.x;
-    b = nb.x;
+    const uint64_t na = nodes[a], nb = nodes[b];
+    if (node_label(na) != node_label(nb)) return false;
+    a = node_parent(na);
+    b = node_parent(nb);
   }
   return true;
 }
@@ -131,15 +143,11 @@ struct Shared {
   Hyp hyp[kBMaxB];
   int child_of[kBMaxB];                 // beam index of h_j's parent prefix, or -1
   uint32_t merged[kBMaxB][kBMaxV / 32]; // (i, c): h_i + c is a beam hypothesis
-  uint64_t stay_key[kBMaxB];
-  uint64_t ext_key[kBMaxB];             // extension of h_j by the frame's top class
-  uint64_t rowmax[kBT / 64];
-  uint64_t bound;
-  uint64_t list[kBList];
+  uint64_t list[kBList + 8];            // (+8: zeros read past the count)
+  uint64_t bkey[2 * kBMaxB];            // stay keys, then extension keys (0 past n)
   uint64_t win[kBMaxB];
-  uint64_t wmax[2][kBT / 64];
-  int cnt, nsel;
-  uint8_t flag[kBT];                    // blank-frame flags of the current 256-frame chunk
+  float spb[kBMaxB], spnb[kBMaxB];      // p_b', p_nb' of the stays
+  int16_t vc[kBMaxV];                   // the frame's classes that can reach the bound
 };
 
 // Candidate (i, c) of the current frame: p_b', p_nb' (stays include the
@@ -164,6 +172,19 @@ __device__ __forceinline__ bool cand(const Shared& sh, int i, int c, int blank, 
   return true;
 }
 
+// Key index of candidate (i, c): i * 1024 + c orders the candidates as
+// i * V + c does (c < V <= 1024), without a division to decode it.
+__device__ __forceinline__ int cand_idx(int i, int c) { return (i << 10) | c; }
+
+// frames of a 64-frame chunk that blank collapse keeps: not a blank frame
+// right after a blank frame (prev: the frame before the chunk was one)
+__device__ __forceinline__ uint64_t kept_frames(uint64_t flags, int nt, bool prev) {
+  const uint64_t valid = nt >= 64 ? ~0ull : ((1ull << nt) - 1ull);
+  return valid & ~(flags & ((flags << 1) | (prev ? 1ull : 0ull)));
+}
+
+// KC: class columns per lane (c = lane + 64k, k < KC), KC*64 >= V.
+template <int KC>
 __global__ void __launch_bounds__(kBT) k_beam(const BeamDesc* __restrict__ descs, int V, int blank,
                                               int B, float thr, int32_t* __restrict__ out_len,
                                               float* __restrict__ out_logp, float* __restrict__ out_scaled,
@@ -171,11 +192,12 @@ __global__ void __launch_bounds__(kBT) k_beam(const BeamDesc* __restrict__ descs
                                               int32_t* __restrict__ out_nkept,
                                               int32_t* __restrict__ out_status) {
   __shared__ Shared sh;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int lane = threadIdx.x;
   const BeamDesc d = descs[blockIdx.x];
+  gf32_t* const y = (gf32_t*)d.y;
   const int u = d.u;
   const int T = d.T;
-  if (tid == 0) {
+  if (lane == 0) {
     Hyp h{};
     h.pb = 1.0f;
     h.pnb = 0.0f;
@@ -192,232 +214,266 @@ __global__ void __launch_bounds__(kBT) k_beam(const BeamDesc* __restrict__ descs
   int E = 0;
   int status = 0;
   int kept = 0;            // frames kept by blank collapse (all of them, also after a failure)
-  bool prev_blank = false;
-  const int words = (V + 31) >> 5;
-  // this thread's classes: c = tid + k*256; their probabilities for the
-  // frame being processed, and prefetched for the next kept frame
-  float yv[kBCols], pre[kBCols];
+  // this lane's classes: their probabilities for the frame being processed,
+  // and prefetched for the next kept frame; -1 past the last class
+  float yv[KC], pre[KC];
   int pre_t = -1;
+  auto load_row = [&](int t, float (&dst)[KC]) {
+    int ln = lane;
+    asm volatile("" : "+v"(ln));   // recomputed per row: no long-lived lane masks
+    const int64_t base = (int64_t)t * V;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int c = ln + k * kBT;
+      const float v = y[base + (c < V ? c : V - 1)];
+      dst[k] = c < V ? v : -1.0f;
+    }
+  };
+  // blank probability of frame t0 + lane (0 past the end)
+  auto blank_p = [&](int t0) -> float {
+    return t0 + lane < T ? y[(int64_t)(t0 + lane) * V + blank] : 0.0f;
+  };
+  uint64_t flags = ballot(blank_p(0) > thr);   // blank frames of the current chunk
+  bool prev_blank = false;                      // the frame before the chunk was a blank frame
   for (int t0 = 0; t0 < T; t0 += kBT) {
-    // blank-frame flags of the next 256 frames, read at once
     const int nt = T - t0 < kBT ? T - t0 : kBT;
-    __syncthreads();   // the previous chunk's flags are no longer read
-    if (tid < nt) sh.flag[tid] = d.y[(int64_t)(t0 + tid) * V + blank] > thr ? 1 : 0;
-    __syncthreads();
-    for (int tt = 0; tt < nt; ++tt) {
+    uint64_t keep = kept_frames(flags, nt, prev_blank);
+    const bool last_blank = (flags >> (nt - 1)) & 1ull;
+    // the next chunk's blank probabilities: loaded now, compared when needed
+    const int t1 = t0 + kBT;
+    const float nbp = blank_p(t1);
+    if (status != 0) {
+      kept += __builtin_popcountll(keep);
+      keep = 0ull;
+    }
+    while (keep != 0ull) {
+      const int tt = __builtin_ctzll(keep);
+      keep &= keep - 1ull;
       const int t = t0 + tt;
-      const bool is_blank = sh.flag[tt] != 0;
-      const bool keep = !(is_blank && prev_blank);
-      prev_blank = is_blank;
-      if (!keep) continue;
       const int ki = kept++;
       if (status != 0) continue;
       // (a) the row (prefetched when this frame was known in time)
       if (pre_t == t) {
 #pragma unroll
-        for (int k = 0; k < kBCols; ++k) yv[k] = pre[k];
+        for (int k = 0; k < KC; ++k) yv[k] = pre[k];
       } else {
-        const float* yt = d.y + (int64_t)t * V;
-#pragma unroll
-        for (int k = 0; k < kBCols; ++k) yv[k] = tid + k * kBT < V ? yt[tid + k * kBT] : 0.0f;
+        load_row(t, yv);
       }
-      // the next kept frame of this chunk, if any: start loading its row
+      // the next kept frame, in this chunk or the next: start loading its row
       {
         int tn = -1;
-        bool pb_ = is_blank;
-        for (int q = tt + 1; q < nt; ++q) {
-          const bool ib = sh.flag[q] != 0;
-          if (!(ib && pb_)) { tn = t0 + q; break; }
-          pb_ = ib;
+        if (keep != 0ull) {
+          tn = t0 + __builtin_ctzll(keep);
+        } else if (t1 < T) {
+          const uint64_t k1 = kept_frames(ballot(nbp > thr), T - t1, last_blank);
+          if (k1 != 0ull) tn = t1 + __builtin_ctzll(k1);
         }
         pre_t = tn;
-        if (tn >= 0) {
-          const float* yn = d.y + (int64_t)tn * V;
+        if (tn >= 0) load_row(tn, pre);
+      }
+      // the row into LDS (every slot up to 64*KC); in registers the blank
+      // then reads -1 like the slots past the last class, and the frame's
+      // most probable non-blank class is the smallest of the largest
+      int ln = lane;
+      asm volatile("" : "+v"(ln));
+      float ymax = -1.0f;
 #pragma unroll
-          for (int k = 0; k < kBCols; ++k) pre[k] = tid + k * kBT < V ? yn[tid + k * kBT] : 0.0f;
+      for (int k = 0; k < KC; ++k) {
+        const int c = ln + k * kBT;
+        sh.row[c] = yv[k];
+        yv[k] = c == blank ? -1.0f : yv[k];
+        ymax = yv[k] > ymax ? yv[k] : ymax;
+      }
+      const float rowmax = __ockl_wfred_max_f32(ymax);
+      int cs = 0;
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        const uint64_t m = ballot(yv[k] == rowmax);
+        if (m != 0ull) {
+          cs = k * kBT + __builtin_ctzll(m);
+          break;
         }
       }
-#pragma unroll
-      for (int k = 0; k < kBCols; ++k)
-        if (tid + k * kBT < V) sh.row[tid + k * kBT] = yv[k];
-      // the frame's most probable non-blank class (ties: the smaller class)
+      // (b) for each h_j the first i whose prefix is h_j's without its last
+      // label: hashes compared for every i at once, then for the matches
+      // the lengths and nodes, and only on a node mismatch the exact walk
+      // (same_chain)
+      for (int w = lane; w < n * (kBMaxV / 32); w += kBT) sh.merged[w / (kBMaxV / 32)][w % (kBMaxV / 32)] = 0u;
+      Hyp hj = sh.hyp[lane < n ? lane : 0];
+      int p = -1;
       {
-        uint64_t best = 0ull;
+        // every slot's hash read (broadcast), the matches as a bit mask
+        // (slots from n on hold stale entries: masked out)
+        uint64_t hash_a[kBMaxB];
 #pragma unroll
-        for (int k = 0; k < kBCols; ++k) {
-          const int c = tid + k * kBT;
-          if (c < V && c != blank) {
-            const uint64_t key = ((uint64_t)__builtin_bit_cast(uint32_t, yv[k]) << 32) |
-                                 (uint64_t)(0xFFFFFFFFu - (uint32_t)c);
-            best = key > best ? key : best;
-          }
-        }
-        best = wave_max(best);
-        if (lane == 0) sh.rowmax[wv] = best;
-      }
-      for (int w = tid; w < n * words; w += kBT) sh.merged[w / words][w % words] = 0u;
-      if (tid < n) {
-        // the first i whose prefix is h_j's without its last label: length
-        // and hash read for every i at once, nodes compared, and only on a
-        // node mismatch the exact walk (parent_is)
-        const Hyp hj = sh.hyp[tid];
-        int p = -1;
+        for (int i = 0; i < kBMaxB; ++i) hash_a[i] = sh.hyp[i].hash;
+        uint32_t mm = 0u;
 #pragma unroll
-        for (int i = 0; i < kBMaxB; ++i) {
+        for (int i = kBMaxB - 1; i >= 0; --i) mm = (mm << 1) | (uint32_t)(hj.phash == hash_a[i]);
+        mm &= lane < n ? (1u << n) - 1u : 0u;
+        while (mm != 0u) {
+          const int i = __builtin_ctz(mm);
+          mm &= mm - 1u;
           const int len_i = sh.hyp[i].len, node_i = sh.hyp[i].node;
-          const uint64_t hash_i = sh.hyp[i].hash;
-          if (p < 0 && i < n && hj.len == len_i + 1 && hj.phash == hash_i &&
-              (hj.pnode == node_i || parent_is(hj, sh.hyp[i], d.nodes)))
+          if (hj.len == len_i + 1 && (hj.pnode == node_i || same_chain(hj.pnode, node_i, (gcu64_t*)d.nodes))) {
             p = i;
+            break;
+          }
         }
-        sh.child_of[tid] = p;
       }
-      if (tid == 0) sh.cnt = 0;
+      if (lane < n) sh.child_of[lane] = p;
       __syncthreads();
-      // (b) merged extensions; stay keys; the extension of each hypothesis by
-      // the frame's most probable class (unless it joins a stay)
-      if (tid < n) {
-        const int p = sh.child_of[tid];
+      // merged extensions: h_p + last_j is h_j
+      if (lane < n && p >= 0) atomicOr(&sh.merged[p][hj.last >> 5], 1u << (hj.last & 31));
+      __syncthreads();
+      // stay keys, and the extension of each hypothesis by the frame's most
+      // probable class unless it joins a stay
+      // (the stay as cand(j, blank) computes it, from this lane's h_j and
+      // parent index; its p_b', p_nb' kept for the next beam)
+      uint64_t sk = 0ull, ek = 0ull;
+      if (lane < n) {
+        const float pb = hj.s * sh.row[blank];
+        float pnb = hj.len > 0 ? hj.pnb * sh.row[hj.last] : 0.0f;
         if (p >= 0) {
-          const int c = sh.hyp[tid].last;
-          atomicOr(&sh.merged[p][c >> 5], 1u << (c & 31));
+          const Hyp& q = sh.hyp[p];
+          const float x = (hj.last == q.last ? q.pb : q.s) * sh.row[hj.last];
+          pnb = pnb + x;
         }
-        float pb, pnb;
-        cand(sh, tid, blank, blank, pb, pnb);
-        sh.stay_key[tid] = make_key(pb + pnb, tid * V + blank);
-        uint64_t rm = 0ull;
-        for (int w = 0; w < kBT / 64; ++w) rm = sh.rowmax[w] > rm ? sh.rowmax[w] : rm;
-        uint64_t ek = 0ull;
-        if (rm != 0ull) {
-          const int cs = (int)(0xFFFFFFFFu - (uint32_t)rm);
-          bool joins = false;
-#pragma unroll
-          for (int k = 0; k < kBMaxB; ++k) {
-            const int ck = sh.child_of[k], lk = sh.hyp[k].last;
-            joins |= k < n && ck == tid && lk == cs;
-          }
-          if (!joins) {
-            const Hyp& h = sh.hyp[tid];
-            ek = make_key(0.0f + (cs == h.last ? h.pb : h.s) * sh.row[cs], tid * V + cs);
-          }
-        }
-        sh.ext_key[tid] = ek;
+        sh.spb[lane] = pb;
+        sh.spnb[lane] = pnb;
+        sk = make_key(pb + pnb, cand_idx(lane, blank));
+        if (!((sh.merged[lane][cs >> 5] >> (cs & 31)) & 1u))
+          ek = make_key(0.0f + (cs == hj.last ? hj.pb : hj.s) * sh.row[cs], cand_idx(lane, cs));
       }
-      __syncthreads();
       // (b2) the bound: the B-th largest of those (up to) 2n distinct
       // candidates' keys -- any B distinct candidates bound the B-th best
-      // key from below; 1 (every positive candidate) when there are fewer
-      if (wv == 0) {
-        uint64_t key = 0ull;
-        if (lane < n) key = sh.stay_key[lane];
-        else if (lane < 2 * n) key = sh.ext_key[lane - n];
-        // the keys are read once (lane q holds key q) and broadcast by
-        // readlane; every lane ranks its own
+      // key from below; 1 (every positive candidate) when there are fewer.
+      // Lane q holds key q (0 from lane 2n on); every lane ranks its own.
+      // Lane q < 32 holds key q (stays, then extensions; 0 past n) and
+      // ranks it against the 2n, read from LDS by broadcast.
+      uint64_t bound = 1ull;
+      {
+        if (lane < kBMaxB) {
+          sh.bkey[lane] = sk;
+          sh.bkey[kBMaxB + lane] = ek;
+        }
+        __syncthreads();
+        const uint64_t key = lane < 2 * kBMaxB ? sh.bkey[lane] : 0ull;
         int rank = 0;
+#pragma unroll 4
+        for (int q = 0; q < n; ++q) rank += (sh.bkey[q] > key ? 1 : 0) + (sh.bkey[kBMaxB + q] > key ? 1 : 0);
+        const int valid = __builtin_popcountll(ballot(key != 0ull));
+        if (valid >= B) {
+          const uint64_t at = ballot(key != 0ull && rank == B - 1);   // exactly one lane
+          if (at != 0ull) bound = lane_u64(key, __builtin_ctzll(at));
+        }
+      }
+      // (c) candidates at or above the bound into the list, appended in lane
+      // order by ballot.  A key at or above the bound needs a total at or
+      // above the bound's float part.  Float products are monotone, so the
+      // largest factor F = max(s_i, p_b_i) over the beam times y[c] bounds
+      // every extension by c (exact pruning, no rounding involved): only
+      // the classes with F*y[c] at or above it are paired with the beam.
+      const float bound_f = __builtin_bit_cast(float, (uint32_t)(bound >> 32));
+      int cnt = 0;
+      auto append = [&](bool ok, uint64_t key) {
+        const uint64_t m = ballot(ok);
+        const int slot = cnt + below(m);
+        if (ok && slot < kBList) sh.list[slot] = key;
+        cnt += __builtin_popcountll(m);
+      };
+      append(lane < n && sk != 0ull && sk >= bound, sk);
+      const float F = __ockl_wfred_max_f32(lane < n ? (hj.s > hj.pb ? hj.s : hj.pb) : 0.0f);
+      int nv = 0;
 #pragma unroll
-        for (int q = 0; q < 2 * kBMaxB; ++q) rank += (q < 2 * n && lane_u64(key, q) > key) ? 1 : 0;
-        const int valid = __builtin_popcountll(__builtin_amdgcn_ballot_w64(key != 0ull));
-        if (lane == 0 && valid < B) sh.bound = 1ull;
-        if (lane < 2 * n && key != 0ull && rank == B - 1 && valid >= B) sh.bound = key;
+      for (int k = 0; k < KC; ++k) {
+        const int c = ln + k * kBT;
+        // y > 0: a class with y = 0 (or past the end, or the blank) gives
+        // no positive total
+        const bool ok = yv[k] > 0.0f && yv[k] * F >= bound_f;
+        const uint64_t m = ballot(ok);
+        if (ok) sh.vc[nv + below(m)] = (int16_t)c;
+        nv += __builtin_popcountll(m);
       }
       __syncthreads();
-      // (c) candidates at or above the bound into the list
-      const uint64_t bound = sh.bound;
-      if (tid < n && sh.stay_key[tid] != 0ull && sh.stay_key[tid] >= bound) {
-        const int slot = atomicAdd(&sh.cnt, 1);
-        if (slot < kBList) sh.list[slot] = sh.stay_key[tid];
-      }
-      // A key at or above the bound needs a total at or above the bound's
-      // float part; float products are monotone, so max(s, p_b) times this
-      // thread's largest probability bounds every extension of a hypothesis
-      // here (exact pruning, no rounding involved).
-      const float bound_f = __builtin_bit_cast(float, (uint32_t)(bound >> 32));
-      float ymax = 0.0f;
-#pragma unroll
-      for (int k = 0; k < kBCols; ++k) {
-        const int c = tid + k * kBT;
-        if (c < V && c != blank) ymax = yv[k] > ymax ? yv[k] : ymax;
-      }
-      for (int i = 0; i < n; ++i) {
-        const Hyp& h = sh.hyp[i];
-        const float hs = h.s, hpb = h.pb;
-        if ((hs > hpb ? hs : hpb) * ymax < bound_f) continue;
-        const int hl = h.last;
-#pragma unroll
-        for (int k = 0; k < kBCols; ++k) {
-          const int c = tid + k * kBT;
-          // extension (i, c): p_b' = 0, p_nb' = x, total 0 + x
-          const float x = (c == hl ? hpb : hs) * yv[k];
-          if (!(x >= bound_f) || c >= V || c == blank) continue;
-          if ((sh.merged[i][c >> 5] >> (c & 31)) & 1u) continue;
-          const uint64_t key = make_key(0.0f + x, i * V + c);
-          if (key >= bound) {
-            const int slot = atomicAdd(&sh.cnt, 1);
-            if (slot < kBList) sh.list[slot] = key;
+      if (nv > 0) {
+        // pairs (i, m): class vc[m] after h_i, m padded to a power of two
+        const int lg = nv <= 1 ? 0 : 32 - __builtin_clz((uint32_t)(nv - 1));
+        const int pairs = n << lg;
+        for (int b0 = 0; b0 < pairs; b0 += kBT) {
+          const int q = b0 + lane, i = q >> lg, m = q & ((1 << lg) - 1);
+          bool ok = false;
+          uint64_t key = 0ull;
+          if (i < n && m < nv) {
+            const int c = sh.vc[m];
+            const Hyp& h = sh.hyp[i];
+            // extension (i, c): p_b' = 0, p_nb' = x, total 0 + x
+            const float x = (c == h.last ? h.pb : h.s) * sh.row[c];
+            if (x >= bound_f && !((sh.merged[i][c >> 5] >> (c & 31)) & 1u)) {
+              key = make_key(0.0f + x, cand_idx(i, c));
+              ok = key >= bound;
+            }
           }
+          append(ok, key);
         }
       }
       __syncthreads();
       // (d) the B best keys, in order
-      const int cnt = sh.cnt;
+      int nsel;
       if (cnt <= kBT) {
-        // rank of each listed key among the listed keys (all distinct)
-        if (tid < cnt) {
-          const uint64_t key = sh.list[tid];
-          int rank = 0;
-          for (int j = 0; j < cnt; ++j) rank += sh.list[j] > key ? 1 : 0;
-          if (rank < B) sh.win[rank] = key;
+        // rank of each listed key among the listed keys (all distinct),
+        // read from LDS by broadcast, 8 at a time (zeros past the count)
+        if (lane < 8) sh.list[cnt + lane] = 0ull;
+        __syncthreads();
+        const uint64_t key = lane < cnt ? sh.list[lane] : 0ull;
+        int rank = 0;
+        for (int q = 0; q < cnt; q += 8) {
+#pragma unroll
+          for (int r = 0; r < 8; ++r) rank += sh.list[q + r] > key ? 1 : 0;
         }
-        if (tid == 0) sh.nsel = cnt < B ? cnt : B;
+        if (lane < cnt && rank < B) sh.win[rank] = key;
+        nsel = cnt < B ? cnt : B;
       } else if (cnt <= kBList) {
-        if (wv == 0) {
-          uint64_t prev = ~0ull;
-          int m = 0;
-          for (int r = 0; r < B; ++r) {
-            uint64_t best = 0ull;
-            for (int q = lane; q < cnt; q += 64) {
-              const uint64_t k = sh.list[q];
-              if (k < prev && k > best) best = k;
-            }
-            best = wave_max(best);
-            if (best == 0ull) break;
-            if (lane == 0) sh.win[r] = best;
-            prev = best;
-            m = r + 1;
+        uint64_t prev = ~0ull;
+        nsel = 0;
+        for (int r = 0; r < B; ++r) {
+          uint64_t best = 0ull;
+          for (int q = lane; q < cnt; q += kBT) {
+            const uint64_t k = sh.list[q];
+            if (k < prev && k > best) best = k;
           }
-          if (lane == 0) sh.nsel = m;
+          best = wave_max(best);
+          if (best == 0ull) break;
+          if (lane == 0) sh.win[r] = best;
+          prev = best;
+          nsel = r + 1;
         }
       } else {
         // the list overflowed: repeated maximum over every candidate
         uint64_t prev = ~0ull;
-        int m = 0;
+        nsel = 0;
         for (int r = 0; r < B; ++r) {
           uint64_t best = 0ull;
-          if (tid < n && sh.stay_key[tid] < prev && sh.stay_key[tid] > best) best = sh.stay_key[tid];
-          for (int k = 0; k < kBCols; ++k) {
-            const int c = tid + k * kBT;
-            if (c >= V || c == blank) continue;
+          if (lane < n && sk < prev && sk > best) best = sk;
+#pragma unroll
+          for (int k = 0; k < KC; ++k) {
+            const int c = ln + k * kBT;
+            if (yv[k] < 0.0f) continue;   // past the last class, or the blank
             for (int i = 0; i < n; ++i) {
               float pb, pnb;
               if (!cand(sh, i, c, blank, pb, pnb)) continue;
-              const uint64_t key = make_key(pb + pnb, i * V + c);
+              const uint64_t key = make_key(pb + pnb, cand_idx(i, c));
               if (key < prev && key > best) best = key;
             }
           }
           best = wave_max(best);
-          if (lane == 0) sh.wmax[r & 1][wv] = best;
-          __syncthreads();
-          best = 0ull;
-          for (int w = 0; w < kBT / 64; ++w) best = sh.wmax[r & 1][w] > best ? sh.wmax[r & 1][w] : best;
           if (best == 0ull) break;
-          if (tid == 0) sh.win[r] = best;
+          if (lane == 0) sh.win[r] = best;
           prev = best;
-          m = r + 1;
+          nsel = r + 1;
         }
-        if (tid == 0) sh.nsel = m;
       }
       __syncthreads();
-      const int nsel = sh.nsel;
       if (nsel == 0) {   // no candidate with a positive total (uniform)
         status = 2;
         continue;
@@ -426,15 +482,21 @@ __global__ void __launch_bounds__(kBT) k_beam(const BeamDesc* __restrict__ descs
       const int e = frexp_exp(__builtin_bit_cast(float, (uint32_t)(sh.win[0] >> 32)));
       E += e;
       Hyp nh;
-      if (tid < nsel) {
-        const int idx = key_index(sh.win[tid]);
-        const int i = idx / V, c = idx - i * V;
-        float pb, pnb;
-        cand(sh, i, c, blank, pb, pnb);
+      if (lane < nsel) {
+        // the winner's p_b', p_nb': a stay's as computed above; an
+        // extension's p_b' = 0 and p_nb' = its total (0 + x = x)
+        const uint64_t wk = sh.win[lane];
+        const int idx = key_index(wk);
+        const int i = idx >> 10, c = idx & 1023;
+        float pb = 0.0f, pnb = __builtin_bit_cast(float, (uint32_t)(wk >> 32));
+        if (c == blank) {
+          pb = sh.spb[i];
+          pnb = sh.spnb[i];
+        }
         nh = sh.hyp[i];
         if (c != blank) {
-          const int node = ki * B + tid;
-          d.nodes[node] = make_int2(nh.node, c);
+          const int node = ki * B + lane;
+          ((gu64_t*)d.nodes)[node] = ((uint64_t)(uint32_t)c << 32) | (uint32_t)nh.node;
           nh.phash = nh.hash;
           nh.hash = hash_ext(nh.hash, c);
           nh.pnode = nh.node;
@@ -447,33 +509,35 @@ __global__ void __launch_bounds__(kBT) k_beam(const BeamDesc* __restrict__ descs
         nh.s = nh.pb + nh.pnb;
       }
       __syncthreads();
-      if (tid < nsel) sh.hyp[tid] = nh;
+      if (lane < nsel) sh.hyp[lane] = nh;
       n = nsel;
-      __syncthreads();   // new beam and its nodes visible to the whole workgroup
+      __syncthreads();   // the new beam, and its nodes, visible to every lane
     }
+    if (t1 < T) flags = ballot(nbp > thr);
+    prev_blank = last_blank;
   }
   // outputs: labels by walking each hypothesis's nodes
   const int B0 = u * B;
-  if (tid < B) {
-    if (status == 0 && tid < n) {
-      const Hyp h = sh.hyp[tid];
+  if (lane < B) {
+    if (status == 0 && lane < n) {
+      const Hyp h = sh.hyp[lane];
       int node = h.node;
       for (int k = h.len - 1; k >= 0; --k) {
-        const int2 nd = d.nodes[node];
-        d.tok[(int64_t)tid * T + k] = nd.y;
-        node = nd.x;
+        const uint64_t nd = ((gcu64_t*)d.nodes)[node];
+        ((gi32_t*)d.tok)[(int64_t)lane * T + k] = node_label(nd);
+        node = node_parent(nd);
       }
-      out_len[B0 + tid] = h.len;
+      out_len[B0 + lane] = h.len;
       const float tot = h.pb + h.pnb;
-      if (out_scaled) out_scaled[B0 + tid] = tot;
-      if (out_logp) out_logp[B0 + tid] = (float)(log((double)tot) + (double)E * 0.69314718055994530942);
+      if (out_scaled) out_scaled[B0 + lane] = tot;
+      if (out_logp) out_logp[B0 + lane] = (float)(log((double)tot) + (double)E * 0.69314718055994530942);
     } else {
-      out_len[B0 + tid] = 0;
-      if (out_scaled) out_scaled[B0 + tid] = 0.0f;
-      if (out_logp) out_logp[B0 + tid] = -__builtin_inff();
+      out_len[B0 + lane] = 0;
+      if (out_scaled) out_scaled[B0 + lane] = 0.0f;
+      if (out_logp) out_logp[B0 + lane] = -__builtin_inff();
     }
   }
-  if (tid == 0) {
+  if (lane == 0) {
     if (out_exp) out_exp[u] = E;
     out_nhyp[u] = status == 0 ? n : 0;
     if (out_nkept) out_nkept[u] = kept;
@@ -562,8 +626,10 @@ int ctcalign_beam_decode(ctcalign_ctx* ctx, int32_t N, const float* probs, const
   }
   BeamDesc* d_desc = reinterpret_cast<BeamDesc*>(ws);
   HIP_TRY(hipMemcpyAsync(d_desc, descs.data(), sizeof(BeamDesc) * N, hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_beam, dim3(N), dim3(kBT), 0, st, d_desc, V, blank, beam, threshold, out_len,
-                     out_logp, out_scaled, out_exp, out_nhyp, out_nkept, out_status);
+  // class columns per lane: the power of two with 64 * KC >= V
+  auto kern = V <= 64 ? k_beam<1> : V <= 128 ? k_beam<2> : V <= 256 ? k_beam<4> : V <= 512 ? k_beam<8> : k_beam<16>;
+  hipLaunchKernelGGL(kern, dim3(N), dim3(kBT), 0, st, d_desc, V, blank, beam, threshold, out_len, out_logp,
+                     out_scaled, out_exp, out_nhyp, out_nkept, out_status);
   HIP_TRY(hipGetLastError());
   if (!workspace) {
     HIP_TRY(hipEventRecord(ctx->arena_ev, st));
