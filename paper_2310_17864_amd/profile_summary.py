@@ -88,7 +88,7 @@ def _per_kernel(path: str, counter: str, pattern: str):
             continue
         d = r["Dispatch_Id"]
         vals[d] = vals.get(d, 0.0) + float(r["Counter_Value"])
-        names[d] = r["Kernel_Name"].split("(")[0]
+        names[d] = _kname(r["Kernel_Name"])
     if not vals:
         raise SystemExit(f"no {counter} rows for kernels matching {pattern!r} in {path}")
     by = {}
@@ -127,6 +127,13 @@ def traffic(fetch_dir: str, write_dir: str, out: str, copy_bytes: int, command: 
 XCDS = 8   # accelerator complex dies of an MI355X: GRBM_GUI_ACTIVE counts on each
 
 
+def _kname(full: str) -> str:
+    """A kernel's name without return type, anonymous namespace or arguments
+    (template arguments kept)."""
+    n = full[5:] if full.startswith("void ") else full
+    return n.replace("(anonymous namespace)::", "").split("(")[0]
+
+
 def counters(d: str, out: str, command: str, kernel: str = "ctca::") -> None:
     path = _find(d, "counter_collection.csv")
     per = {}      # (kernel, counter) -> {dispatch: value}
@@ -134,7 +141,7 @@ def counters(d: str, out: str, command: str, kernel: str = "ctca::") -> None:
     for r in csv.DictReader(open(path)):
         if kernel not in r["Kernel_Name"]:
             continue
-        k = r["Kernel_Name"].split("(")[0]
+        k = _kname(r["Kernel_Name"])
         key = (k, r["Counter_Name"])
         disp = per.setdefault(key, {})
         disp[r["Dispatch_Id"]] = disp.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
