@@ -4,7 +4,8 @@ its labels, their count, the exact scaled total and power-of-two exponent of
 every hypothesis, the kept-frame count and the status -- bit for bit; the
 log-probabilities within float32 rounding of the double-precision log.
 Covers tiny exhaustive cases, exact ties, one-hot frames, every beam width up
-to 16, class counts up to 1024, a non-zero blank, collapse thresholds from
+to 16, class counts up to 1024 (each side of every 64-class column
+boundary the kernel is instantiated for), a non-zero blank, collapse thresholds from
 none to aggressive, flat rows that overflow the candidate list, long inputs,
 failures (no positive candidate), and the decoding workload's shapes."""
 import numpy as np
@@ -89,7 +90,8 @@ def test_beam_widths(beam):
     assert _compare(_pack(ys), 0, beam, 1.0, f"B{beam}") == []
 
 
-@pytest.mark.parametrize("V,blank", [(2, 0), (2, 1), (31, 30), (256, 0), (500, 0), (1000, 7), (1024, 1023)])
+@pytest.mark.parametrize("V,blank", [(2, 0), (2, 1), (31, 30), (64, 63), (65, 64), (100, 3), (128, 0), (129, 128),
+                                     (256, 0), (257, 1), (500, 0), (512, 511), (513, 0), (1000, 7), (1024, 1023)])
 def test_class_counts(V, blank):
     rng = np.random.default_rng(V)
     ys = [random_probs(rng, int(rng.integers(3, 80)), V, conc=0.05) for _ in range(8)]
