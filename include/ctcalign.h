@@ -333,8 +333,8 @@ int ctcalign_align_batched(ctcalign_ctx *ctx, int32_t N,
  *   out_nkept[i]              frames kept by blank collapse (nullable)
  *   out_status[i]             0, or 2 when no prefix keeps a positive
  *                             probability (out_nhyp = 0)
- * Limits: 2 <= V <= 1024, 1 <= beam <= 16.  One workgroup per utterance, all
- * utterances in one launch on `stream`.  workspace (device, 256-byte
+ * Limits: 2 <= V <= 1024, 1 <= beam <= 16.  One wavefront (a 64-thread
+ * workgroup) per utterance, all utterances in one launch on `stream`.  workspace (device, 256-byte
  * aligned, >= ctcalign_beam_workspace_bytes) may be NULL: the context's
  * arena is used, ordered across streams as for ctcalign_align_ex.
  * Errors: EINVAL (arguments), ENOMEM, EDEVICE. */
