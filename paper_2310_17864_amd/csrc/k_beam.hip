@@ -210,6 +210,7 @@ __global__ void __launch_bounds__(kBT) k_beam(const BeamDesc* __restrict__ descs
     h.phash = 0;
     sh.hyp[0] = h;
   }
+  __syncthreads();
   int n = 1;
   int E = 0;
   int status = 0;
